@@ -1,0 +1,192 @@
+"""Throughput of the LOS-dependent P0/P2/P4 estimator on one MI355X.
+
+One step = the whole estimator (catalogue scalars, row sort, LOS-weighted assignment
+fused with the x FFT, y FFT with z-power grouping, z FFT fused with the k-hat
+contraction and shell binning, finalize) on one synthetic clustered RSD mock that is
+already resident in HBM, ending with the FP64 P_l on the host.
+
+Default workload: lognormal RSD mock, P(k) = 2e4 (k/0.1)^-1.5, 512^3 field, L = 2500
+Mpc/h at 2000 Mpc/h, nbar = 3e-4 (~4.7e6 galaxies), Kaiser f = 0.75, b = 2, 20x randoms
+(~9.4e7), FKP P0 = 1e4, CIC on 512^3, ell = 0, 2, 4, 128 bins of width 2 k_f.
+
+Prints one JSON line (value = mocks per second).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def plan_bytes(cfg, n_gal, n_ran):
+    """Algorithmic HBM bytes of each stage (each input byte read once, each output written once)."""
+    N, dn, nbins, ell = cfg["N"], cfg["dn"], cfg["nbins"], cfg["ell_max"]
+    K = nbins * dn
+    TK = 8 if N >= 1024 else min(16, N // 2)
+    Kx = -(-K // TK) * TK
+    hstride = 0
+    for kt in range(Kx // TK):
+        M = math.isqrt(K * K - 1 - (kt * TK) ** 2)
+        hstride += N * (2 * M + 1) * TK
+    G = {0: 1, 2: 7, 4: 22}[ell]
+    ngroups = {0: 1, 2: 4, 4: 9}[ell]
+    X = G * N * N * Kx * 8
+    H = ngroups * hstride * 8
+    Np = n_gal + n_ran
+    return {
+        "scalars": 4 * n_gal + 8 * n_ran,
+        "sort": 12 * Np + 16 * Np + 16 * Np + 3 * 4 * N * N,
+        "assign_x": 16 * Np + 4 * (N * N + 1) + X,
+        "fft_y": X + H,
+        "fft_z_bin": H,
+    }
+
+
+def make_workload(name):
+    from paper_1505_05341_amd import catalogs
+    if name == "clustered_512":
+        gal, ran, cfg = catalogs.clustered_rsd_512()
+        desc = ("lognormal RSD mock, 512^3 field, L=2500 Mpc/h at 2000 Mpc/h, nbar=3e-4, f=0.75, b=2, "
+                "20x randoms, FKP P0=1e4; CIC 512^3, ell=0,2,4, 128 bins of 2 k_f")
+    elif name == "tiny_32":
+        gal, ran, cfg = catalogs.tiny_plain()
+        desc = "2000 uniform galaxies + 20000 randoms, 1000 Mpc/h cube at 1500 Mpc/h; CIC 32^3, ell=0,2,4"
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    return gal, ran, cfg, desc
+
+
+def cpu_baseline(gal, ran, cfg):
+    """The FP64 oracle on a bounded sample of the same workload: the catalogue scalars plus
+    one of the 22 LOS-weighted grids (assignment + 3D FFT); per-mock time = scalars +
+    22 x (assignment + FFT). The contraction and binning are left out (the real oracle is
+    slower still)."""
+    from oracle import estimator as est
+    c = est.Config(**cfg)
+    t0 = time.perf_counter()
+    alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar, c.norm_from)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    wp = est.signed_weights(gal.w, ran.w, alpha)
+    rh = est.unit_los(pos, c.observer, c.los)
+    t1 = time.perf_counter()
+    g = est.assign_to_grid(pos, wp * rh[:, 0] * rh[:, 0], c)
+    t2 = time.perf_counter()
+    gk = est.fft3(g)
+    t3 = time.perf_counter()
+    del g, gk, pos, wp, rh
+    ngrid = len(est.los_monomials(c.ell_max))
+    per_mock = (t1 - t0) + ngrid * ((t2 - t1) + (t3 - t2))
+    return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": 1, "kind": "oracle",
+            "sample": ("catalogue scalars + 1 of %d LOS-weighted grids (FP64 CIC assignment of all %d particles "
+                       "+ 3D FFT of %d^3), per-mock time = scalars + %d x (assign + FFT) = %.1f s; numpy/pocketfft "
+                       "single-threaded; contraction and binning not counted"
+                       % (ngrid, gal.n + ran.n, c.N, ngrid, per_mock)),
+            "measured_s": t3 - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clustered_512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1505_05341_amd as pk
+    from paper_1505_05341_amd import native
+
+    log("generating workload", args.workload)
+    t = time.perf_counter()
+    gal, ran, cfg, desc = make_workload(args.workload)
+    log("generated %d galaxies + %d randoms in %.1f s" % (gal.n, ran.n, time.perf_counter() - t))
+    torch.cuda.set_device(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t
+    h2d_bytes = 20 * (gal.n + ran.n)
+    ws = pk.Workspace()
+    log("workspace %.2f GB" % (native.workspace_size(cfg, gal.n, ran.n) / 1e9))
+
+    for i in range(args.warmup):
+        pk.pk_multipoles(g, r, cfg, ws)
+        log("warmup", i)
+    native.set_stage_timing(True)
+    stage_sum = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = pk.pk_multipoles(g, r, cfg, ws)
+        for k, v in native.stage_times().items():
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    native.set_stage_timing(False)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    log("stage ms", json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
+    byts = plan_bytes(cfg, gal.n, ran.n)
+    dom = max((k for k in byts), key=lambda k: stage_ms.get(k, 0.0))
+    achieved = byts[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    stage_gbs = {k: round(byts[k] / (stage_ms[k] * 1e-3) / 1e9, 1) for k in byts if stage_ms.get(k, 0) > 0}
+    log("stage GB/s", json.dumps(stage_gbs))
+    value = 1e3 / ms_per_step
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        cpu = cpu_baseline(gal, ran, cfg)
+        log("oracle sample took %.1f s" % cpu.pop("measured_s"))
+
+    out = {
+        "metric": "P0/P2/P4 mocks/sec at 512^3 and 1024^3 grid; achieved HBM GB/s vs peak",
+        "value": value,
+        "unit": "mocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "grid": cfg["N"], "n_gal": gal.n, "n_ran": ran.n,
+                   "ell_max": cfg["ell_max"], "assign": "CIC" if cfg["assign"] == 2 else "TSC",
+                   "nbins": cfg["nbins"], "dn": cfg["dn"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "kernel_ms": stage_ms[dom], "algorithmic_bytes": byts[dom]},
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stages_GBps": stage_gbs,
+        "h2d_GBps": h2d_bytes / h2d_s / 1e9,
+        "cpu_baseline": cpu,
+        "P_check": {"P0_bin1": res["P0"][1], "P2_bin1": res["P2"][1], "P4_bin1": res["P4"][1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

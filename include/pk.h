@@ -1,0 +1,169 @@
+/*
+ * pk.h -- C interface of libpk: line-of-sight-dependent power-spectrum multipoles
+ * (P_0, P_2, P_4) of a galaxy catalogue with the FFT implementation of the Yamamoto
+ * estimator (Bianchi, Gil-Marin, Ruggeri & Percival 2015), on one AMD MI355X (gfx950).
+ *
+ * What is computed (the paper's statement of the problem):
+ *   Sec. 2, Eq. (1)   the FKP field F = w (n - alpha n_s) of galaxies and randoms, with
+ *                     alpha = sum_g w / sum_r w and I = int w^2 nbar^2 dr;
+ *   Sec. 3, Eq. (5)   A_n(k) = int (khat . rhat)^n F(r) e^{ik.r} dr, each particle using
+ *                     its own line of sight rhat = (x - observer)/|x - observer|;
+ *   Sec. 3, Eqs. (9)-(13)  A_2 and A_4 from the FFTs of 6 and 15 grids F rhat_i rhat_j
+ *                     and F rhat_i^2 rhat_j rhat_l (1, 7 or 22 FFTs for ell_max 0, 2, 4);
+ *   Sec. 3, Eqs. (6)-(8)   P_0 = <|A_0|^2>/I - noise, P_2 = 5/(2I) <A_0 (3A_2 - A_0)^*>,
+ *                     P_4 = 9/(8I) <A_0 (35 A_4 - 30 A_2 + 3 A_0)^*>, shell-averaged;
+ *   Sec. 2, Eq. (3)   shot noise subtracted from ell = 0 only;
+ *   Sec. 4            cloud-in-cell (or triangular-shaped-cloud) assignment on a
+ *                     periodic cube, corrected for the assignment window (Jing 2005).
+ *
+ * Discrete readings (where the paper leaves a choice):
+ *   alpha = sum_g w / sum_r w;  I = alpha sum_r w^2 nbar (norm_from = 0) or
+ *   sum_g w^2 nbar (norm_from = 1);  S = sum_g w^2 + alpha^2 sum_r w^2.
+ *   Nodes at box_min + j H, H = L/N. CIC: i = floor(u), weights (1-f, f) on (i, i+1).
+ *   TSC: i = floor(u + 1/2), d = u - i, weights (1/2 (1/2-d)^2, 3/4 - d^2, 1/2 (1/2+d)^2)
+ *   on (i-1, i, i+1). Indices wrap modulo N.
+ *   A mode n (integer vector, components in [-N/2, N/2)) belongs to bin b when
+ *   b dn <= |n| < (b+1) dn (exact integer test on |n|^2); n = 0 is excluded.
+ *   compensate = 0: no correction, noise S; 1: divide by W^2, noise S;
+ *   2 (default): divide by W^2 and subtract the aliased noise S prod_i C_p(n_i) / W^2,
+ *   W = prod_i sinc^p(pi n_i / N), p = 2 (CIC) or 3 (TSC),
+ *   C_2 = 1 - 2/3 s^2, C_3 = 1 - s^2 + 2/15 s^4, s = sin(pi n_i / N).
+ *
+ * Memory: every device pointer below is borrowed and read only; the library
+ * allocates no device memory. All scratch lives in the caller's workspace, sized by
+ * pk_workspace_size(), and all work is queued on the caller's HIP stream.
+ * Calls that share a workspace must not overlap.
+ */
+#ifndef PK_H
+#define PK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pk_status;
+
+#define PK_OK 0
+#define PK_EINVAL (-1)      /* null pointer, bad enum, dn < 1, L <= 0, nbins*dn > N/2, n < 0, nbar missing */
+#define PK_ERANGE (-2)      /* a particle outside [box_min, box_min + L) on some axis */
+#define PK_EDOM (-3)        /* non-finite xyz / w / nbar, a particle at the observer, sum_r w = 0, I <= 0 */
+#define PK_EWORKSPACE (-4)  /* workspace null or smaller than pk_workspace_size() */
+#define PK_EDEVICE (-5)     /* a HIP runtime error */
+#define PK_ENOTSUP (-6)     /* N not a supported FFT size, or more than 2^31 - 1 particles */
+
+#define PK_CIC 2
+#define PK_TSC 3
+
+/* One catalogue, in device memory.
+ *   xyz   float32 (n, 3) row-major positions, same coordinates as box_min and observer
+ *   w     float32 (n) weights
+ *   nbar  float32 (n) expected number density at each point; may be NULL when the
+ *         normalisation does not read it (galaxies with norm_from = 0, randoms with
+ *         norm_from = 1)
+ *   n     number of points (>= 0) */
+typedef struct {
+  const float* xyz;
+  const float* w;
+  const float* nbar;
+  int64_t n;
+} pk_catalog;
+
+/* Estimator configuration (host memory). */
+typedef struct {
+  int32_t N;           /* grid side: 8, 16, 32, 64, 128, 256, 512 or 1024 */
+  int32_t assign;      /* PK_CIC or PK_TSC */
+  int32_t ell_max;     /* 0, 2 or 4 -> 1, 7 or 22 LOS-weighted grids */
+  int32_t los;         /* 0: each particle's own line of sight; 1: fixed +z (plane-parallel) */
+  int32_t compensate;  /* 0, 1 or 2 (see above) */
+  int32_t dn;          /* bin width in units of the fundamental mode 2 pi / L, >= 1 */
+  int32_t nbins;       /* number of bins, nbins * dn <= N / 2 */
+  int32_t norm_from;   /* 0: I from the randoms, 1: I from the galaxies */
+  double box_min[3];   /* lower corner of the periodic FFT cube */
+  double L;            /* side of the cube */
+  double observer[3];  /* origin of the lines of sight */
+} pk_config;
+
+/* Results (host memory, caller-owned arrays).
+ *   k_eff[nbins]   mode-averaged |k| of each bin (0 for an empty bin)
+ *   P[(ell_max/2 + 1) * nbins]  P_0 then P_2 then P_4, bin-fastest (0 for an empty bin)
+ *   noise[nbins]   shell mean of the noise subtracted from P_0, divided by I
+ *   nmodes[nbins]  number of modes of the full N^3 lattice in each bin
+ * Scalars alpha, I and S (sum_g w^2 + alpha^2 sum_r w^2) are filled in. Any array
+ * pointer may be NULL to skip it. On error nothing is written. */
+typedef struct {
+  double* k_eff;
+  double* P;
+  double* noise;
+  int64_t* nmodes;
+  double alpha;
+  double I;
+  double S;
+} pk_result;
+
+/* Bytes of device workspace pk_multipoles needs for this configuration and these
+ * catalogue sizes. Returns PK_EINVAL / PK_ENOTSUP for an invalid configuration. */
+pk_status pk_workspace_size(const pk_config* cfg, int64_t n_gal, int64_t n_ran, size_t* bytes);
+
+/* The whole estimator: catalogue scalars, LOS-weighted assignment, the batched FFTs,
+ * the k-hat contraction, shell binning, shot noise and normalisation. Queues all work
+ * on `hip_stream` (a hipStream_t; NULL = the default stream), then waits for it and
+ * copies the FP64 results to `out`. `workspace` is device memory of at least
+ * pk_workspace_size() bytes, 256-byte aligned; its prior contents do not matter. */
+pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
+                        void* workspace, size_t workspace_bytes, pk_result* out, void* hip_stream);
+
+/* Asynchronous form: queues the same work and leaves the results in device memory at
+ * `d_result` (float64, pk_result_doubles(cfg) values: k_eff[nbins], P[(ell_max/2+1) nbins],
+ * noise[nbins], nmodes[nbins] (as doubles), then alpha, I, S and the error-flag word).
+ * Returns after queueing; input errors found on the device appear only in the flag word
+ * (bit 1 non-finite position, 2 out of box, 4 particle at the observer, 8 non-finite
+ * weight or nbar, 16 sum_r w = 0 or I <= 0). Launch-time errors are returned. */
+pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
+                              void* workspace, size_t workspace_bytes, double* d_result,
+                              void* hip_stream);
+
+/* Number of doubles pk_multipoles_async writes. */
+int64_t pk_result_doubles(const pk_config* cfg);
+
+/* Stage entry point for tests: runs the catalogue scalars, the row sort and the fused
+ * LOS-weighted assignment with the FFT along x, then stops, leaving the x-transformed
+ * grids in the workspace (same kernels as pk_multipoles). Queued on `hip_stream`. */
+pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
+                          void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Where pk_stage_xgrids leaves grid `m`: complex64 values X[z][y][kx] for kx < kx_count,
+ * x-transformed (unnormalised, e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at
+ * byte `offset` of the workspace. Monomial m has exponents (a, b, c) of rhat_x, rhat_y,
+ * rhat_z as returned by pk_monomial. */
+pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
+                          size_t* offset, int32_t* kx_count);
+
+/* Stage timing, for measurement. While enabled (process-wide, not thread-safe), each
+ * pk_multipoles / pk_multipoles_async call records HIP events on its stream around its
+ * stages: 0 workspace init, 1 catalogue scalars, 2 row sort, 3 LOS assignment + x FFT,
+ * 4 y FFT + z-power grouping, 5 z FFT + contraction + binning, 6 finalize.
+ * pk_stage_times waits for the last call's events and writes up to n durations in
+ * milliseconds; it returns the number of stages (7), or -1 if timing has no record. */
+pk_status pk_set_stage_timing(int32_t enable);
+int32_t pk_stage_times(double* ms, int32_t n);
+const char* pk_stage_name(int32_t i);
+
+/* Number of LOS-weighted grids for ell_max (1, 7, 22), and the exponents of grid m. */
+int32_t pk_num_grids(int32_t ell_max);
+pk_status pk_monomial(int32_t m, int32_t* a, int32_t* b, int32_t* c);
+
+/* Static description of a status code. */
+const char* pk_status_string(pk_status s);
+
+/* Detail of the last error on the calling thread, copied into buf (NUL-terminated,
+ * truncated to n bytes). Returns the full length of the message. */
+size_t pk_last_error(char* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PK_H */

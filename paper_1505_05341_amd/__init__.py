@@ -1,0 +1,8 @@
+"""LOS-dependent power-spectrum multipoles (P0, P2, P4) with FFTs on AMD MI355X.
+
+A from-scratch HIP implementation of the FFT-based Yamamoto estimator of Bianchi,
+Gil-Marin, Ruggeri & Percival (2015). The C interface is include/pk.h (libpk.so);
+this package is its Python binding plus the seeded synthetic catalogue generators.
+"""
+from .native import PkError, load  # noqa: F401
+from .api import DeviceCatalog, Workspace, pk_multipoles, stage_xgrids, xgrid_view  # noqa: F401

@@ -1,0 +1,120 @@
+"""Python front end of libpk: P_0, P_2, P_4 of device-resident catalogues.
+
+    import torch, paper_1505_05341_amd as pk
+    gal = pk.DeviceCatalog.from_host(gal_np)        # or pk.DeviceCatalog(pos, w, nbar)
+    ran = pk.DeviceCatalog.from_host(ran_np)
+    res = pk.pk_multipoles(gal, ran, cfg)            # cfg: dict of the C configuration fields
+
+All arithmetic happens in the library's HIP kernels (include/pk.h); torch only holds
+device memory and supplies the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import native
+
+
+@dataclass
+class DeviceCatalog:
+    pos: "object"          # torch float32 (n, 3) on the GPU
+    w: "object"            # torch float32 (n,)
+    nbar: "object" = None  # torch float32 (n,) or None
+
+    @property
+    def n(self):
+        return int(self.pos.shape[0])
+
+    @staticmethod
+    def from_host(cat, device="cuda"):
+        import torch
+        pos = torch.from_numpy(np.ascontiguousarray(cat.pos, dtype=np.float32)).to(device)
+        w = torch.from_numpy(np.ascontiguousarray(cat.w, dtype=np.float32)).to(device)
+        nbar = None
+        if getattr(cat, "nbar", None) is not None:
+            nbar = torch.from_numpy(np.ascontiguousarray(cat.nbar, dtype=np.float32)).to(device)
+        return DeviceCatalog(pos, w, nbar)
+
+    def c_struct(self):
+        return native.make_catalog(self.pos, self.w, self.nbar)
+
+
+class Workspace:
+    """Reusable device workspace (a torch uint8 buffer), grown on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _result_dict(cfg, k, P, noise, nm, res):
+    nb = cfg.nbins
+    out = {"k_eff": k, "nmodes": nm, "noise": noise, "alpha": res.alpha, "I": res.I, "S": res.S}
+    for j, ell in enumerate(range(0, cfg.ell_max + 1, 2)):
+        out["P%d" % ell] = P[j * nb:(j + 1) * nb].copy()
+    return out
+
+
+def pk_multipoles(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None,
+                  stream=None):
+    """Runs the estimator; returns k_eff, P0 [, P2, P4], noise, nmodes, alpha, I, S."""
+    lib = native.load()
+    c = native.make_config(cfg)
+    cg, cr = gal.c_struct(), ran.c_struct()
+    nbytes = native.workspace_size(cfg, gal.n, ran.n)
+    ws = (workspace or Workspace()).get(nbytes)
+    nb = c.nbins
+    nl = c.ell_max // 2 + 1
+    k = np.zeros(nb)
+    P = np.zeros(nb * nl)
+    noise = np.zeros(nb)
+    nm = np.zeros(nb, dtype=np.int64)
+    res = native.PkResult()
+    dp = ctypes.POINTER(ctypes.c_double)
+    res.k_eff = k.ctypes.data_as(dp)
+    res.P = P.ctypes.data_as(dp)
+    res.noise = noise.ctypes.data_as(dp)
+    res.nmodes = nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    s = stream if stream is not None else native.current_stream()
+    native.check(lib.pk_multipoles(ctypes.byref(c), ctypes.byref(cg), ctypes.byref(cr),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(res), s))
+    return _result_dict(c, k, P, noise, nm, res)
+
+
+def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
+    """Runs up to the fused assignment + x transform and returns (workspace tensor, layout),
+    layout[m] = (byte offset, kx_count) of grid m (complex64 X[z][y][kx])."""
+    import torch
+    lib = native.load()
+    c = native.make_config(cfg)
+    nbytes = native.workspace_size(cfg, gal.n, ran.n)
+    ws = (workspace or Workspace()).get(nbytes)
+    native.check(lib.pk_stage_xgrids(ctypes.byref(c), ctypes.byref(gal.c_struct()), ctypes.byref(ran.c_struct()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), native.current_stream()))
+    torch.cuda.synchronize()
+    layout = {}
+    for m in range(native.num_grids(c.ell_max)):
+        off = ctypes.c_size_t()
+        kx = ctypes.c_int32()
+        native.check(lib.pk_xgrid_layout(ctypes.byref(c), gal.n, ran.n, m, ctypes.byref(off), ctypes.byref(kx)))
+        layout[m] = (int(off.value), int(kx.value))
+    return ws, layout
+
+
+def xgrid_view(ws, layout, m, N):
+    """complex64 view X[z][y][kx] of grid m inside the workspace returned by stage_xgrids."""
+    import torch
+    off, kx = layout[m]
+    nbytes = N * N * kx * 8
+    raw = ws[off:off + nbytes]
+    return raw.view(torch.float32).view(N, N, kx, 2)

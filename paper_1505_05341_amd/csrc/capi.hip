@@ -1,0 +1,366 @@
+// C interface of libpk: configuration checks, the workspace plan and the sequence of
+// stages on the caller's stream (declared in include/pk.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace pk {
+
+static thread_local std::string g_last_error;
+
+static pk_status fail(pk_status st, const std::string& why) {
+  g_last_error = why;
+  return st;
+}
+
+static int num_grids_for(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
+
+static int64_t isqrt64(int64_t n) {
+  if (n <= 0) return 0;
+  int64_t s = (int64_t)sqrt((double)n);
+  while (s * s > n) --s;
+  while ((s + 1) * (s + 1) <= n) ++s;
+  return s;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static bool supported_N(int N) {
+  return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
+}
+
+pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* plan, const char** why) {
+  static const char* msg = "";
+  *why = msg;
+  if (!cfg) return fail(PK_EINVAL, "null configuration");
+  Plan& p = *plan;
+  memset(&p, 0, sizeof(Plan));
+  p.N = cfg->N;
+  p.assign = cfg->assign;
+  p.ell_max = cfg->ell_max;
+  p.los = cfg->los;
+  p.compensate = cfg->compensate;
+  p.dn = cfg->dn;
+  p.nbins = cfg->nbins;
+  p.norm_from = cfg->norm_from;
+  for (int i = 0; i < 3; ++i) {
+    p.box_min[i] = cfg->box_min[i];
+    p.observer[i] = cfg->observer[i];
+  }
+  p.L = cfg->L;
+  p.n_gal = n_gal;
+  p.n_ran = n_ran;
+  if (!supported_N(p.N)) return fail(PK_ENOTSUP, "N must be one of 8, 16, 32, 64, 128, 256, 512, 1024");
+  if (p.assign != PK_CIC && p.assign != PK_TSC) return fail(PK_EINVAL, "assign must be 2 (CIC) or 3 (TSC)");
+  if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(PK_EINVAL, "ell_max must be 0, 2 or 4");
+  if (p.los != 0 && p.los != 1) return fail(PK_EINVAL, "los must be 0 or 1");
+  if (p.compensate < 0 || p.compensate > 2) return fail(PK_EINVAL, "compensate must be 0, 1 or 2");
+  if (p.norm_from != 0 && p.norm_from != 1) return fail(PK_EINVAL, "norm_from must be 0 or 1");
+  if (p.dn < 1) return fail(PK_EINVAL, "dn must be >= 1");
+  if (p.nbins < 1 || (int64_t)p.nbins * p.dn > p.N / 2) return fail(PK_EINVAL, "need 1 <= nbins and nbins * dn <= N / 2");
+  if (!(p.L > 0.0) || !isfinite(p.L)) return fail(PK_EINVAL, "L must be positive and finite");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(p.box_min[i]) || !isfinite(p.observer[i])) return fail(PK_EINVAL, "box_min and observer must be finite");
+  if (n_gal < 0 || n_ran < 0) return fail(PK_EINVAL, "catalogue sizes must be >= 0");
+  if (n_gal + n_ran > (int64_t)0x7fffffff) return fail(PK_ENOTSUP, "at most 2^31 - 1 particles per call");
+
+  p.G = num_grids_for(p.ell_max);
+  p.K = p.nbins * p.dn;
+  p.TK = p.N >= 1024 ? 8 : (p.N / 2 < 16 ? p.N / 2 : 16);   // must match tile_cols<N>() of the FFT passes
+  p.Kx = ((p.K + p.TK - 1) / p.TK) * p.TK;
+  p.nkt = p.Kx / p.TK;
+  // tiles: the y pass keeps |ky| <= M(kt) with kx0^2 + ky^2 < K^2, kx0 = kt * TK
+  int64_t reg = 0, items = 0;
+  for (int kt = 0; kt < p.nkt; ++kt) {
+    const int64_t kx0 = (int64_t)kt * p.TK;
+    const int64_t M = isqrt64((int64_t)p.K * p.K - 1 - kx0 * kx0);
+    p.tiles.M[kt] = (int)M;
+    p.tiles.regoff[kt] = reg;
+    p.tiles.item0[kt] = items;
+    reg += (int64_t)p.N * (2 * M + 1) * p.TK;
+    items += 2 * M + 1;
+  }
+  p.tiles.item0[p.nkt] = items;
+  p.H_group_stride = (size_t)reg;
+  p.z_items = items;
+  p.z_blocks = (int)(items < 512 ? items : 512);
+
+  // groups (n, c) and their members (grid index, a, b, multinomial weight)
+  GroupTable& gt = p.groups;
+  gt.ngroups = 0;
+  for (int n = 0; n <= p.ell_max; n += 2) {
+    for (int c = 0; c <= n; ++c) {
+      const int g = gt.ngroups++;
+      gt.n[g] = n;
+      gt.c[g] = c;
+      gt.count[g] = 0;
+      for (int m = 0; m < p.G; ++m) {
+        const Monomial mo = monomial(m);
+        if (mo.a + mo.b + mo.c != n || mo.c != c) continue;
+        static const int fact[5] = {1, 1, 2, 6, 24};
+        const int s = gt.count[g]++;
+        gt.grid[g][s] = m;
+        gt.a[g][s] = mo.a;
+        gt.b[g][s] = mo.b;
+        gt.coef[g][s] = (float)(fact[n] / (fact[mo.a] * fact[mo.b] * fact[mo.c]));
+      }
+    }
+  }
+
+  const int nl = p.ell_max / 2 + 1;
+  p.result_doubles = (int64_t)p.nbins * (3 + nl) + 4;
+  const int64_t nrow = (int64_t)p.N * p.N;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  p.off_scalars = take(sizeof(double) * 16);
+  p.off_partials = take(sizeof(double) * 6 * kStatsBlocks);
+  p.off_flags = take(64);
+  p.off_tw = take(sizeof(float) * 2 * p.N);
+  p.off_invw2 = take(sizeof(float) * p.N);
+  p.off_alias = take(sizeof(float) * p.N);
+  p.off_tables = take(sizeof(GroupTable) + sizeof(TileTable));
+  p.off_rowcnt = take(sizeof(uint32_t) * nrow);
+  p.off_rowoff = take(sizeof(uint32_t) * (nrow + 1));
+  p.off_blocksum = take(sizeof(uint32_t) * 1024);
+  p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
+  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * nrow * p.Kx);
+  p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);
+  p.off_zpart = take(sizeof(double) * kNumSums * (size_t)p.z_blocks * p.nbins);
+  p.off_result = take(sizeof(double) * (size_t)p.result_doubles);
+  p.total = off;
+  return PK_OK;
+}
+
+static pk_status check_catalog(const pk_catalog* c, bool need_nbar, const char* name) {
+  if (!c) return fail(PK_EINVAL, std::string("null ") + name + " catalogue");
+  if (c->n < 0) return fail(PK_EINVAL, std::string(name) + ".n < 0");
+  if (c->n > 0 && (!c->xyz || !c->w)) return fail(PK_EINVAL, std::string(name) + ": null xyz or w");
+  if (c->n > 0 && need_nbar && !c->nbar) return fail(PK_EINVAL, std::string(name) + ": nbar is needed by the normalisation");
+  return PK_OK;
+}
+
+static pk_status hip_fail(hipError_t e, const char* where) {
+  return fail(PK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static pk_status prepare(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* ws,
+                         size_t ws_bytes, Plan* p) {
+  pk_status st = check_catalog(gal, cfg && cfg->norm_from == 1, "galaxy");
+  if (st != PK_OK) return st;
+  st = check_catalog(ran, cfg && cfg->norm_from == 0, "random");
+  if (st != PK_OK) return st;
+  const char* why;
+  st = make_plan(cfg, gal->n, ran->n, p, &why);
+  if (st != PK_OK) return st;
+  if (!ws || ws_bytes < p->total)
+    return fail(PK_EWORKSPACE, "workspace needs " + std::to_string(p->total) + " bytes, got " + std::to_string(ws_bytes));
+  if (((uintptr_t)ws & 255) != 0) return fail(PK_EWORKSPACE, "workspace must be 256-byte aligned");
+  return PK_OK;
+}
+
+// Stage timing (measurement only): events recorded between the stages of a call.
+constexpr int kNumStages = 7;
+static const char* kStageNames[kNumStages] = {"init", "scalars", "sort", "assign_x", "fft_y", "fft_z_bin",
+                                               "finalize"};
+static struct {
+  bool enabled = false;
+  bool recorded = false;
+  int device = -1;
+  hipEvent_t ev[kNumStages + 1] = {};
+} g_timing;
+
+static void mark(int i, hipStream_t s) {
+  if (g_timing.enabled && g_timing.ev[i]) hipEventRecord(g_timing.ev[i], s);
+}
+
+static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, double* d_result,
+                            hipStream_t s, bool stop_after_x) {
+  hipError_t e;
+  const bool timed = g_timing.enabled && !stop_after_x;
+  if (timed) {
+    int dev = -1;
+    hipGetDevice(&dev);
+    if (g_timing.device != dev) {
+      for (int i = 0; i <= kNumStages; ++i)
+        if (hipEventCreate(&g_timing.ev[i]) != hipSuccess) g_timing.ev[i] = nullptr;
+      g_timing.device = dev;
+    }
+    g_timing.recorded = false;
+  }
+  if (timed) mark(0, s);
+  if ((e = launch_init(p, ws, s)) != hipSuccess) return hip_fail(e, "init");
+  if (timed) mark(1, s);
+  if ((e = launch_stats(p, gal, ran, ws, s)) != hipSuccess) return hip_fail(e, "catalogue scalars");
+  if (timed) mark(2, s);
+  if ((e = launch_sort(p, gal, ran, ws, s)) != hipSuccess) return hip_fail(e, "row sort");
+  if (timed) mark(3, s);
+  if ((e = launch_xpass(p, ws, s)) != hipSuccess) return hip_fail(e, "assignment and x transform");
+  if (stop_after_x) return PK_OK;
+  if (timed) mark(4, s);
+  if ((e = launch_ypass(p, ws, s)) != hipSuccess) return hip_fail(e, "y transform");
+  if (timed) mark(5, s);
+  if ((e = launch_zpass(p, ws, s)) != hipSuccess) return hip_fail(e, "z transform and binning");
+  if (timed) mark(6, s);
+  if ((e = launch_finalize(p, ws, d_result, s)) != hipSuccess) return hip_fail(e, "finalize");
+  if (timed) {
+    mark(7, s);
+    g_timing.recorded = true;
+  }
+  return PK_OK;
+}
+
+static pk_status flags_status(int flags) {
+  if (flags & kFlagOutOfBox) return fail(PK_ERANGE, "a particle lies outside [box_min, box_min + L)");
+  if (flags & kFlagNonFinitePos) return fail(PK_EDOM, "a particle position is not finite");
+  if (flags & kFlagAtObserver) return fail(PK_EDOM, "a particle sits at the observer (no line of sight)");
+  if (flags & kFlagNonFiniteWeight) return fail(PK_EDOM, "a weight or nbar is not finite");
+  if (flags & kFlagBadNorm) return fail(PK_EDOM, "sum of random weights is 0 or the normalisation I is not positive");
+  return PK_OK;
+}
+
+}  // namespace pk
+
+using namespace pk;
+
+extern "C" {
+
+pk_status pk_workspace_size(const pk_config* cfg, int64_t n_gal, int64_t n_ran, size_t* bytes) {
+  if (!bytes) return fail(PK_EINVAL, "null bytes pointer");
+  Plan p;
+  const char* why;
+  const pk_status st = make_plan(cfg, n_gal, n_ran, &p, &why);
+  if (st != PK_OK) return st;
+  *bytes = p.total;
+  return PK_OK;
+}
+
+int64_t pk_result_doubles(const pk_config* cfg) {
+  if (!cfg || (cfg->ell_max != 0 && cfg->ell_max != 2 && cfg->ell_max != 4) || cfg->nbins < 1) return -1;
+  return (int64_t)cfg->nbins * (3 + cfg->ell_max / 2 + 1) + 4;
+}
+
+pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                              size_t workspace_bytes, double* d_result, void* hip_stream) {
+  Plan p;
+  pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
+  if (st != PK_OK) return st;
+  if (!d_result) return fail(PK_EINVAL, "null result pointer");
+  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), d_result, (hipStream_t)hip_stream, false);
+}
+
+pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                        size_t workspace_bytes, pk_result* out, void* hip_stream) {
+  Plan p;
+  pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
+  if (st != PK_OK) return st;
+  if (!out) return fail(PK_EINVAL, "null result");
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* d_res = at<double>(ws, p.off_result);
+  st = run_stages(p, *gal, *ran, ws, d_res, s, false);
+  if (st != PK_OK) return st;
+  std::vector<double> h((size_t)p.result_doubles);
+  hipError_t e = hipMemcpyAsync(h.data(), d_res, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "result copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  const int nb = p.nbins, nl = p.ell_max / 2 + 1;
+  const double* tail = h.data() + (size_t)nb * (3 + nl);
+  st = flags_status((int)tail[3]);
+  if (st != PK_OK) return st;
+  if (out->k_eff) memcpy(out->k_eff, h.data(), sizeof(double) * nb);
+  if (out->P) memcpy(out->P, h.data() + nb, sizeof(double) * nb * nl);
+  if (out->noise) memcpy(out->noise, h.data() + (size_t)nb * (1 + nl), sizeof(double) * nb);
+  if (out->nmodes)
+    for (int b = 0; b < nb; ++b) out->nmodes[b] = (int64_t)h[(size_t)nb * (2 + nl) + b];
+  out->alpha = tail[0];
+  out->I = tail[1];
+  out->S = tail[2];
+  return PK_OK;
+}
+
+pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                          size_t workspace_bytes, void* hip_stream) {
+  Plan p;
+  pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
+  if (st != PK_OK) return st;
+  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), nullptr, (hipStream_t)hip_stream, true);
+}
+
+pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m, size_t* offset,
+                          int32_t* kx_count) {
+  Plan p;
+  const char* why;
+  pk_status st = make_plan(cfg, n_gal, n_ran, &p, &why);
+  if (st != PK_OK) return st;
+  if (m < 0 || m >= p.G) return fail(PK_EINVAL, "grid index out of range");
+  if (!offset || !kx_count) return fail(PK_EINVAL, "null output pointer");
+  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.N * p.N * p.Kx;
+  *kx_count = p.Kx;
+  return PK_OK;
+}
+
+pk_status pk_set_stage_timing(int32_t enable) {
+  g_timing.enabled = enable != 0;
+  return PK_OK;
+}
+
+int32_t pk_stage_times(double* ms, int32_t n) {
+  if (!g_timing.recorded) return -1;
+  if (hipEventSynchronize(g_timing.ev[kNumStages]) != hipSuccess) return -1;
+  for (int i = 0; i < kNumStages && i < n; ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, g_timing.ev[i], g_timing.ev[i + 1]) != hipSuccess) return -1;
+    if (ms) ms[i] = t;
+  }
+  return kNumStages;
+}
+
+const char* pk_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : "?"; }
+
+int32_t pk_num_grids(int32_t ell_max) {
+  return (ell_max == 0 || ell_max == 2 || ell_max == 4) ? num_grids_for(ell_max) : -1;
+}
+
+pk_status pk_monomial(int32_t m, int32_t* a, int32_t* b, int32_t* c) {
+  if (m < 0 || m >= kMaxGrids || !a || !b || !c) return fail(PK_EINVAL, "bad monomial index or null pointer");
+  const Monomial mo = monomial(m);
+  *a = mo.a;
+  *b = mo.b;
+  *c = mo.c;
+  return PK_OK;
+}
+
+const char* pk_status_string(pk_status s) {
+  switch (s) {
+    case PK_OK: return "ok";
+    case PK_EINVAL: return "invalid argument";
+    case PK_ERANGE: return "particle outside the box";
+    case PK_EDOM: return "invalid input value";
+    case PK_EWORKSPACE: return "workspace too small";
+    case PK_EDEVICE: return "HIP runtime error";
+    case PK_ENOTSUP: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+size_t pk_last_error(char* buf, size_t n) {
+  if (buf && n > 0) {
+    const size_t k = g_last_error.size() < n - 1 ? g_last_error.size() : n - 1;
+    memcpy(buf, g_last_error.data(), k);
+    buf[k] = '\0';
+  }
+  return g_last_error.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// LOS-weighted mass assignment fused with the FFT along x (Sec. 3, Eqs. 11 and 13;
+// Sec. 4 for the assignment).
+//
+// One block owns one target grid row (y, z) for a group of the 1, 7 or 22 monomial
+// grids F rhat^m. It reads the particles of the source rows whose stencil reaches
+// (y, z) -- rows were made contiguous by the counting sort -- and for each particle
+// computes its own line of sight rhat = (x - observer)/|x - observer|, the monomials
+// rhat^m, and adds w' W(x) rhat^m into an LDS copy of the row of every grid with LDS
+// atomics. The finished rows never go to HBM in real space: two real rows are packed
+// as one complex row, transformed along x in registers and LDS, separated into their
+// two half spectra, and only kx < Kx is written (every mode with |kx| >= Kx lies
+// outside the binned sphere).
+#include <hip/hip_runtime.h>
+
+#include "fft_dev.hpp"
+#include "particle.hpp"
+#include "plan.hpp"
+
+namespace pk {
+
+struct XArgs {
+  float bmin[3];
+  float invH;
+  float obs[3];
+  int los;
+  int Kx;
+  int64_t grid_stride;  // float2 elements per grid of X: N * N * Kx
+};
+
+__host__ __device__ constexpr int num_grids(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
+
+// Monomials rhat^m in the fixed order (degree 0; degree 2: xx xy xz yy yz zz;
+// degree 4: each as the product of two degree-2 values).
+template <int G>
+__device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&m)[G]) {
+  m[0] = 1.0f;
+  if (G == 1) return;
+  const float xx = rx * rx, xy = rx * ry, xz = rx * rz, yy = ry * ry, yz = ry * rz, zz = rz * rz;
+  m[1] = xx; m[2] = xy; m[3] = xz; m[4] = yy; m[5] = yz; m[6] = zz;
+  if (G == 7) return;
+  m[7] = xx * xx;  m[8] = xx * xy;  m[9] = xx * xz;  m[10] = xx * yy; m[11] = xx * yz;
+  m[12] = xx * zz; m[13] = xy * yy; m[14] = xy * yz; m[15] = xy * zz; m[16] = xz * zz;
+  m[17] = yy * yy; m[18] = yy * yz; m[19] = yy * zz; m[20] = yz * zz; m[21] = zz * zz;
+}
+
+template <int N, int ASSIGN, int G, int G0, int NG>
+__device__ __forceinline__ void deposit(float* __restrict__ rows, const float4 q, int oy, int oz, const XArgs& a) {
+  constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
+  constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
+  const float uy = grid_coord(q.y, a.bmin[1], a.invH);
+  const float uz = grid_coord(q.z, a.bmin[2], a.invH);
+  const float ux = grid_coord(q.x, a.bmin[0], a.invH);
+  const float wyz = q.w * stencil_weight<ASSIGN>(base_offset<ASSIGN>(uy), oy) *
+                    stencil_weight<ASSIGN>(base_offset<ASSIGN>(uz), oz);
+  const int ix = base_index<ASSIGN>(ux, N);
+  const float fx = base_offset<ASSIGN>(ux);
+  float rx = 0.0f, ry = 0.0f, rz = 1.0f;
+  if (a.los == 0) {
+    const float dx = q.x - a.obs[0], dy = q.y - a.obs[1], dz = q.z - a.obs[2];
+    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+    rx = dx * inv; ry = dy * inv; rz = dz * inv;
+  }
+  float m[G];
+  monomials<G>(rx, ry, rz, m);
+#pragma unroll
+  for (int o = 0; o < S; ++o) {
+    const int cell = (ix + O0 + o) & (N - 1);
+    const float v = wyz * stencil_weight<ASSIGN>(fx, O0 + o);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) atomicAdd(&rows[g * N + cell], v * m[G0 + g]);
+  }
+}
+
+// LDS slot of index i of one transform: an XOR swizzle inside each block of 16
+// that spreads the stride-R writes of the first exchange over the banks.
+struct XSwizzle {
+  __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
+};
+
+constexpr int XTHREADS = 512;
+
+template <int N, int ASSIGN, int ELL, int SPLIT>
+__global__ __launch_bounds__(XTHREADS) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
+                                                    const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
+  constexpr int G = num_grids(ELL);
+  constexpr int GB = (G + SPLIT - 1) / SPLIT;
+  constexpr int NP = (GB + 1) / 2;
+  constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
+  constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
+  using F = Fft<N>;
+  static_assert(NP * F::T <= XTHREADS, "row pairs do not fit the block");
+  extern __shared__ float lds[];
+  const int tid = threadIdx.x;
+  const int y = blockIdx.x, z = blockIdx.y, part = blockIdx.z;
+  const int g0 = part * GB;
+  const int ng = G - g0 < GB ? G - g0 : GB;
+
+  for (int i = tid; i < 2 * NP * N; i += blockDim.x) lds[i] = 0.0f;
+
+  // source rows: the particles whose base cell (iy, iz) = (y - oy, z - oz) reach this row
+  uint32_t beg[S * S], pre[S * S + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int s = 0; s < S * S; ++s) {
+    const int oy = O0 + s % S, oz = O0 + s / S;
+    const int sy = (y - oy) & (N - 1), sz = (z - oz) & (N - 1);
+    const int64_t r = (int64_t)sz * N + sy;
+    beg[s] = rowoff[r];
+    pre[s + 1] = pre[s] + (rowoff[r + 1] - beg[s]);
+  }
+  __syncthreads();
+  const uint32_t total = pre[S * S];
+  for (uint32_t f = tid; f < total; f += blockDim.x) {
+    int s = 0;
+    uint32_t b0 = beg[0], p0 = 0;
+#pragma unroll
+    for (int k = 1; k < S * S; ++k) {
+      if (f >= pre[k]) {
+        s = k;
+        b0 = beg[k];
+        p0 = pre[k];
+      }
+    }
+    const float4 q = sorted[b0 + (f - p0)];
+    const int oy = O0 + s % S, oz = O0 + s / S;
+    if (SPLIT == 1) {
+      deposit<N, ASSIGN, G, 0, G>(lds, q, oy, oz, a);
+    } else if (part == 0) {
+      deposit<N, ASSIGN, G, 0, GB>(lds, q, oy, oz, a);
+    } else {
+      deposit<N, ASSIGN, G, GB, G - GB>(lds, q, oy, oz, a);
+    }
+  }
+  __syncthreads();
+
+  // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
+  const int npairs = (ng + 1) / 2;
+  const int q = tid / F::T, t = tid % F::T;
+  const bool active = q < npairs;
+  float2* T = reinterpret_cast<float2*>(lds);  // pair q uses T[q N, (q + 1) N), its two rows
+  float2 d[F::E];
+  if (active) {
+    const float* r0 = lds + 2 * q * N;
+    const float* r1 = r0 + N;
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+      const int x = F::in_index(t, e);
+      d[e] = make_float2(r0[x], r1[x]);
+    }
+  }
+  float2* Tq = T + (active ? q * N : 0);
+  F::run(d, t, tw, Tq, XSwizzle(), active);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) Tq[XSwizzle()(F::out_index(t, e))] = d[e];
+  }
+  __syncthreads();
+  // X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = -i (Z[k] - conj Z[N-k]) / 2
+  const int Kx = a.Kx;
+  const size_t row = ((size_t)z * N + y) * (size_t)Kx;
+  for (int e = tid; e < npairs * Kx; e += blockDim.x) {
+    const int qq = e / Kx, kx = e - qq * Kx;
+    const float2 zk = T[qq * N + XSwizzle()(kx)];
+    const float2 zm = T[qq * N + XSwizzle()((N - kx) & (N - 1))];
+    const int ga = g0 + 2 * qq;
+    X[(size_t)ga * a.grid_stride + row + kx] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (2 * qq + 1 < ng)
+      X[(size_t)(ga + 1) * a.grid_stride + row + kx] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+  }
+}
+
+template <int N, int ASSIGN, int ELL>
+static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
+  constexpr int G = num_grids(ELL);
+  constexpr int SPLIT = (N >= 1024 && G > 16) ? 2 : 1;
+  constexpr int GB = (G + SPLIT - 1) / SPLIT;
+  constexpr int NP = (GB + 1) / 2;
+  const size_t shmem = (size_t)2 * NP * N * sizeof(float);
+  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, N, SPLIT), dim3(XTHREADS), shmem, s,
+                     at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
+                     at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);
+  return hipGetLastError();
+}
+
+template <int N, int ASSIGN>
+static hipError_t launch_x2(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
+  switch (p.ell_max) {
+    case 0: return launch_x3<N, ASSIGN, 0>(p, ws, a, s);
+    case 2: return launch_x3<N, ASSIGN, 2>(p, ws, a, s);
+    default: return launch_x3<N, ASSIGN, 4>(p, ws, a, s);
+  }
+}
+
+template <int N>
+static hipError_t launch_x1(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
+  return p.assign == PK_CIC ? launch_x2<N, PK_CIC>(p, ws, a, s) : launch_x2<N, PK_TSC>(p, ws, a, s);
+}
+
+hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s) {
+  XArgs a;
+  for (int i = 0; i < 3; ++i) {
+    a.bmin[i] = (float)p.box_min[i];
+    a.obs[i] = (float)p.observer[i];
+  }
+  a.invH = (float)((double)p.N / p.L);
+  a.los = p.los;
+  a.Kx = p.Kx;
+  a.grid_stride = (int64_t)p.N * p.N * p.Kx;
+  switch (p.N) {
+    case 8: return launch_x1<8>(p, ws, a, s);
+    case 16: return launch_x1<16>(p, ws, a, s);
+    case 32: return launch_x1<32>(p, ws, a, s);
+    case 64: return launch_x1<64>(p, ws, a, s);
+    case 128: return launch_x1<128>(p, ws, a, s);
+    case 256: return launch_x1<256>(p, ws, a, s);
+    case 512: return launch_x1<512>(p, ws, a, s);
+    case 1024: return launch_x1<1024>(p, ws, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pk

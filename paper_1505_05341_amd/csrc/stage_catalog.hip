@@ -1,0 +1,380 @@
+// Catalogue stages: workspace initialisation, the FP64 catalogue scalars (Sec. 2:
+// alpha, I and the shot-noise amplitude of Eq. 3), input validation, the counting
+// sort of particles by grid row, and the final FP64 reduction into P_0, P_2, P_4
+// (Sec. 3, Eqs. 6-8).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include "plan.hpp"
+#include "particle.hpp"
+
+namespace pk {
+
+// --------------------------------------------------------------------------------
+// Workspace initialisation: flags, row counters, the FFT twiddle table and the
+// per-axis window tables, all computed here in FP64 and stored as FP32.
+// --------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void init_kernel(int N, int assign, int* flags, uint32_t* rowcnt,
+                                                   float2* tw, float* invw2, float* alias) {
+  const int64_t nrow = (int64_t)N * N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += stride) rowcnt[i] = 0u;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *flags = 0;
+  if (t < N) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)N, &s, &c);   // exp(-2 pi i t / N)
+    tw[t] = make_float2((float)c, (float)s);
+    const int n = t < N / 2 ? t : t - N;
+    const double x = (double)n / (double)N;           // in units of pi
+    const double sn = sinpi(x);
+    const double sinc = n == 0 ? 1.0 : sn / (M_PI * x);
+    double w = sinc * sinc;                            // sinc^2 (CIC window)
+    if (assign == PK_TSC) w *= sinc;                   // sinc^3 (TSC window)
+    invw2[t] = (float)(1.0 / (w * w));
+    const double s2 = sn * sn;
+    const double C = assign == PK_CIC ? 1.0 - (2.0 / 3.0) * s2 : 1.0 - s2 + (2.0 / 15.0) * s2 * s2;
+    alias[t] = (float)C;
+  }
+}
+
+// Copies the group and tile tables (passed by value as 32-bit words) into the workspace.
+struct TableWords {
+  uint32_t w[(sizeof(GroupTable) + sizeof(TileTable) + 3) / 4];
+};
+
+__global__ __launch_bounds__(256) void copy_tables_kernel(const TableWords tw, uint32_t* out) {
+  constexpr int n = sizeof(TableWords) / 4;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = tw.w[i];
+}
+
+hipError_t launch_init(const Plan& p, char* ws, hipStream_t s) {
+  TableWords words;
+  memset(&words, 0, sizeof(words));
+  memcpy(&words, &p.groups, sizeof(GroupTable));
+  memcpy(reinterpret_cast<char*>(&words) + sizeof(GroupTable), &p.tiles, sizeof(TileTable));
+  hipLaunchKernelGGL(copy_tables_kernel, dim3(1), dim3(256), 0, s, words, at<uint32_t>(ws, p.off_tables));
+  const int64_t nrow = (int64_t)p.N * p.N;
+  int blocks = (int)((nrow + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks * 256 < p.N) blocks = (p.N + 255) / 256;
+  hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, p.N, p.assign, at<int>(ws, p.off_flags),
+                     at<uint32_t>(ws, p.off_rowcnt), at<float2>(ws, p.off_tw), at<float>(ws, p.off_invw2),
+                     at<float>(ws, p.off_alias));
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------------
+// Catalogue scalars (Sec. 2). Per-block FP64 partial sums in a fixed order, then a
+// single block adds the partials in block order: the result does not depend on
+// scheduling.
+// --------------------------------------------------------------------------------
+__device__ __forceinline__ bool finite_f(float v) { return isfinite(v); }
+
+__global__ __launch_bounds__(256) void stats_kernel(pk_catalog gal, pk_catalog ran, int norm_from,
+                                                    double* partials, int* flags) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < gal.n; i += stride) {
+    const float w = gal.w[i];
+    bad |= !finite_f(w);
+    const double wd = w;
+    acc[0] += wd;
+    acc[2] += wd * wd;
+    if (norm_from == 1) {
+      const float nb = gal.nbar[i];
+      bad |= !finite_f(nb);
+      acc[4] += wd * wd * (double)nb;
+    }
+  }
+  for (int64_t i = t0; i < ran.n; i += stride) {
+    const float w = ran.w[i];
+    bad |= !finite_f(w);
+    const double wd = w;
+    acc[1] += wd;
+    acc[3] += wd * wd;
+    if (norm_from == 0) {
+      const float nb = ran.nbar[i];
+      bad |= !finite_f(nb);
+      acc[5] += wd * wd * (double)nb;
+    }
+  }
+  if (bad) atomicOr(flags, (int)kFlagNonFiniteWeight);
+  __shared__ double red[6][256];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) partials[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void stats_final_kernel(const double* partials, int nblk, int norm_from, double* scal, int* flags) {
+  __shared__ double sums[6];
+  const int k = threadIdx.x;
+  if (k < 6) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partials[b * 6 + k];
+    sums[k] = s;
+  }
+  __syncthreads();
+  if (k == 0) {
+    for (int j = 0; j < 6; ++j) scal[kSumWg + j] = sums[j];
+    const double alpha = sums[0] / sums[1];
+    const double I = norm_from == 0 ? alpha * sums[5] : sums[4];
+    const double S = sums[2] + alpha * alpha * sums[3];
+    scal[kAlpha] = alpha;
+    scal[kNormI] = I;
+    scal[kNoiseS] = S;
+    if (!(sums[1] != 0.0) || !isfinite(alpha) || !(I > 0.0) || !isfinite(I) || !isfinite(S))
+      atomicOr(flags, (int)kFlagBadNorm);
+  }
+}
+
+hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s) {
+  hipLaunchKernelGGL(stats_kernel, dim3(kStatsBlocks), dim3(256), 0, s, gal, ran, p.norm_from,
+                     at<double>(ws, p.off_partials), at<int>(ws, p.off_flags));
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, at<double>(ws, p.off_partials),
+                     kStatsBlocks, p.norm_from, at<double>(ws, p.off_scalars), at<int>(ws, p.off_flags));
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------------
+// Counting sort of the particles by grid row (y, z): histogram, exclusive scan,
+// scatter of (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1).
+// Invalid particles are flagged and left out; the host turns a flag into an error.
+// --------------------------------------------------------------------------------
+struct SortGeom {
+  float bmin[3];
+  float invH;
+  double bmin_d[3];
+  double L;
+  double obs_d[3];
+  int N;
+  int los;
+};
+
+// The one validity test of both sort passes (they must agree particle by particle).
+template <bool RAISE>
+__device__ __forceinline__ bool valid_particle(const SortGeom& g, float x, float y, float z, int* flags) {
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    if (RAISE) atomicOr(flags, (int)kFlagNonFinitePos);
+    return false;
+  }
+  const double dx = (double)x - g.bmin_d[0], dy = (double)y - g.bmin_d[1], dz = (double)z - g.bmin_d[2];
+  if (!(dx >= 0.0 && dx < g.L && dy >= 0.0 && dy < g.L && dz >= 0.0 && dz < g.L)) {
+    if (RAISE) atomicOr(flags, (int)kFlagOutOfBox);
+    return false;
+  }
+  if (g.los == 0) {
+    const double ox = (double)x - g.obs_d[0], oy = (double)y - g.obs_d[1], oz = (double)z - g.obs_d[2];
+    if (ox * ox + oy * oy + oz * oz == 0.0) {
+      if (RAISE) atomicOr(flags, (int)kFlagAtObserver);
+      return false;
+    }
+  }
+  return true;
+}
+
+template <int ASSIGN>
+__global__ __launch_bounds__(256) void hist_kernel(pk_catalog gal, pk_catalog ran, SortGeom g, uint32_t* rowcnt,
+                                                   int* flags) {
+  const int64_t ntot = gal.n + ran.n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
+    const float* q = i < gal.n ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
+    const float x = q[0], y = q[1], z = q[2];
+    if (!valid_particle<true>(g, x, y, z, flags)) continue;
+    const int iy = base_index<ASSIGN>(grid_coord(y, g.bmin[1], g.invH), g.N);
+    const int iz = base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N);
+    atomicAdd(&rowcnt[(int64_t)iz * g.N + iy], 1u);
+  }
+}
+
+template <int ASSIGN>
+__global__ __launch_bounds__(256) void scatter_kernel(pk_catalog gal, pk_catalog ran, SortGeom g,
+                                                      uint32_t* cursor, const double* scal, float4* sorted) {
+  const int64_t ntot = gal.n + ran.n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const float alpha = (float)scal[kAlpha];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
+    const bool isg = i < gal.n;
+    const float* q = isg ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
+    const float x = q[0], y = q[1], z = q[2];
+    if (!valid_particle<false>(g, x, y, z, nullptr)) continue;  // flags were raised by the histogram
+    const int iy = base_index<ASSIGN>(grid_coord(y, g.bmin[1], g.invH), g.N);
+    const int iz = base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N);
+    const uint32_t slot = atomicAdd(&cursor[(int64_t)iz * g.N + iy], 1u);
+    const float w = isg ? gal.w[i] : -alpha * ran.w[i - gal.n];
+    if (slot < (uint32_t)ntot) sorted[slot] = make_float4(x, y, z, w);
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* cnt, int64_t n, uint32_t* blocksum) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t s = 0;
+  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+    const int64_t i = base + k;
+    if (i < n) s += cnt[i];
+  }
+  __shared__ uint32_t red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of up to 1024 block sums in one block.
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* blocksum, int nb) {
+  __shared__ uint32_t a[1024];
+  const int t = threadIdx.x;
+  const uint32_t v = t < nb ? blocksum[t] : 0u;
+  a[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t add = t >= off ? a[t - off] : 0u;
+    __syncthreads();
+    a[t] += add;
+    __syncthreads();
+  }
+  if (t < nb) blocksum[t] = a[t] - v;
+}
+
+// Row offsets and the per-row write cursors (the counters are overwritten in place).
+__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* cnt_cursor, int64_t n, const uint32_t* blocksum,
+                                                        uint32_t* rowoff) {
+  constexpr int PER = kScanChunk / 256;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * PER;
+  uint32_t v[PER];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? cnt_cursor[i] : 0u;
+    s += v[k];
+  }
+  __shared__ uint32_t a[256];
+  a[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = (int)threadIdx.x >= off ? a[threadIdx.x - off] : 0u;
+    __syncthreads();
+    a[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = a[threadIdx.x] - s + blocksum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t i = base + k;
+    if (i < n) {
+      rowoff[i] = run;
+      cnt_cursor[i] = run;
+    }
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) rowoff[n] = run;
+}
+
+static SortGeom sort_geom(const Plan& p) {
+  SortGeom g;
+  for (int i = 0; i < 3; ++i) {
+    g.bmin[i] = (float)p.box_min[i];
+    g.bmin_d[i] = p.box_min[i];
+    g.obs_d[i] = p.observer[i];
+  }
+  g.invH = (float)((double)p.N / p.L);
+  g.L = p.L;
+  g.N = p.N;
+  g.los = p.los;
+  return g;
+}
+
+hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s) {
+  const SortGeom g = sort_geom(p);
+  const int64_t ntot = p.n_gal + p.n_ran;
+  int blocks = (int)((ntot + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  uint32_t* rowcnt = at<uint32_t>(ws, p.off_rowcnt);
+  if (p.assign == PK_CIC)
+    hipLaunchKernelGGL(hist_kernel<PK_CIC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt, at<int>(ws, p.off_flags));
+  else
+    hipLaunchKernelGGL(hist_kernel<PK_TSC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt, at<int>(ws, p.off_flags));
+  const int64_t nrow = (int64_t)p.N * p.N;
+  const int nb = (int)((nrow + kScanChunk - 1) / kScanChunk);
+  uint32_t* bsum = at<uint32_t>(ws, p.off_blocksum);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, rowcnt, nrow, bsum);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(256), 0, s, rowcnt, nrow, bsum, at<uint32_t>(ws, p.off_rowoff));
+  if (p.assign == PK_CIC)
+    hipLaunchKernelGGL(scatter_kernel<PK_CIC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt,
+                       at<double>(ws, p.off_scalars), at<float4>(ws, p.off_sorted));
+  else
+    hipLaunchKernelGGL(scatter_kernel<PK_TSC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt,
+                       at<double>(ws, p.off_scalars), at<float4>(ws, p.off_sorted));
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------------
+// Final reduction (Sec. 3, Eqs. 6-8): per-bin sums over the z-pass blocks in block
+// order, then the Legendre combinations, the noise on ell = 0 only and 1/I.
+// Result layout: k_eff[nb], P[(ell_max/2+1) nb], noise[nb], nmodes[nb], alpha, I, S, flags.
+// --------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int zblocks, int nbins, int ell_max,
+                                                       double kf, const double* scal, const int* flags,
+                                                       double* res) {
+  const double I = scal[kNormI];
+  const int nl = ell_max / 2 + 1;
+  double* k_eff = res;
+  double* P = res + nbins;
+  double* noise = P + (size_t)nl * nbins;
+  double* nmodes = noise + nbins;
+  double* tail = nmodes + nbins;
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    double s[kNumSums] = {0, 0, 0, 0, 0, 0};
+    for (int blk = 0; blk < zblocks; ++blk) {
+      const double* q = zpart + ((size_t)blk * nbins + b) * kNumSums;
+#pragma unroll
+      for (int j = 0; j < kNumSums; ++j) s[j] += q[j];
+    }
+    const double cnt = s[0];
+    if (cnt > 0.0) {
+      const double den = I * cnt;
+      k_eff[b] = kf * s[1] / cnt;
+      P[b] = (s[2] - s[5]) / den;
+      if (nl > 1) P[nbins + b] = 2.5 * (3.0 * s[3] - s[2]) / den;
+      if (nl > 2) P[2 * nbins + b] = 1.125 * (35.0 * s[4] - 30.0 * s[3] + 3.0 * s[2]) / den;
+      noise[b] = s[5] / den;
+    } else {
+      k_eff[b] = 0.0;
+      for (int l = 0; l < nl; ++l) P[l * nbins + b] = 0.0;
+      noise[b] = 0.0;
+    }
+    nmodes[b] = cnt;
+  }
+  if (threadIdx.x == 0) {
+    tail[0] = scal[kAlpha];
+    tail[1] = scal[kNormI];
+    tail[2] = scal[kNoiseS];
+    tail[3] = (double)*flags;
+  }
+}
+
+hipError_t launch_finalize(const Plan& p, char* ws, double* d_result, hipStream_t s) {
+  const double kf = 2.0 * M_PI / p.L;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, at<double>(ws, p.off_zpart), p.z_blocks, p.nbins,
+                     p.ell_max, kf, at<double>(ws, p.off_scalars), at<int>(ws, p.off_flags), d_result);
+  return hipGetLastError();
+}
+
+}  // namespace pk

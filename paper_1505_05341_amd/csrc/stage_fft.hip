@@ -1,0 +1,369 @@
+// Transforms along y and z, the k-hat contraction and the shell binning
+// (Sec. 3, Eqs. 6-13).
+//
+// y pass: one block owns a tile of TK kx columns at one z. For every monomial grid it
+//   loads the N x TK tile (TK complex values per row, coalesced), transforms along y
+//   and multiplies by coef_m tx^a ty^b; the grids of one group (degree n, power c of
+//   z) are summed in registers, so each group leaves a single grid H_{n,c}. Only the
+//   rows with kx0^2 + ky^2 < K^2 are stored (kx0 = the tile's smallest kx).
+// z pass: a persistent block walks (kx tile, ky) columns. It transforms H_{0,0}
+//   along z to A_0, accumulates A_2 = |t|^-2 sum_c tz^c FFT_z[H_{2,c}] and
+//   A_4 = |t|^-4 sum_c tz^c FFT_z[H_{4,c}] (t = 2n/N), and adds per mode
+//   mu Re[A_0 A_l^*] / W^2, the noise and the mode count to FP64 bin sums in LDS
+//   (mu = 1 on the kx = 0 plane, 2 elsewhere: the other half of the lattice holds the
+//   complex conjugates). Each block writes its bin sums once.
+//
+// By linearity, A_n = |t|^-n sum_{a+b+c=n} coef tx^a ty^b tz^c FFT_xyz[F rhat^(a,b,c)]
+// equals the paper's Eqs. (10) and (12); regrouping by the power of z only moves the
+// kx, ky factors in front of the z transform.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+
+#include "fft_dev.hpp"
+#include "plan.hpp"
+
+namespace pk {
+
+struct YArgs {
+  int Kx;
+  int64_t x_grid_stride;
+  int64_t h_group_stride;
+  const GroupTable* gt;   // device copies (dynamic indexing of by-value kernel
+  const TileTable* tt;    // arguments would push them to scratch)
+};
+
+__device__ __forceinline__ float ipow(float x, int e) {
+  float r = 1.0f;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+// LDS slot of row `idx` of column `c`: rows of TK complex values (128 bytes for
+// TK = 16), so a wave touching 16 columns of 4 rows is conflict-free.
+template <int TK>
+struct ColSlot {
+  int c;
+  __device__ __forceinline__ int operator()(int idx) const { return idx * TK + c; }
+};
+
+// kx columns per tile: 16 (128-byte rows) up to N = 512; 8 at N = 1024, where a
+// 16-column tile would need 1024-thread blocks and their 128-register cap.
+template <int N>
+constexpr int tile_cols() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }
+
+template <int N, int TK>
+__global__ __launch_bounds__(TK * Fft<N>::T) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
+                                                              const float2* __restrict__ tw, const YArgs a) {
+  using F = Fft<N>;
+  extern __shared__ float2 T[];
+  const int tid = threadIdx.x;
+  const int c = tid % TK, t = tid / TK;
+  const int kt = blockIdx.x, z = blockIdx.y;
+  const int kx = kt * TK + c;
+  const float tx = (float)kx * (2.0f / N);
+  const GroupTable& gt = *a.gt;
+  const int M = a.tt->M[kt];
+  const int64_t regoff = a.tt->regoff[kt];
+  const int nslot = 2 * M + 1;
+  const int Kx = a.Kx;
+  const ColSlot<TK> slot{c};
+  float tyv[F::E];
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) tyv[e] = (float)signed_freq<N>(F::out_index(t, e)) * (2.0f / N);
+  const int ngroups = gt.ngroups;
+  for (int g = 0; g < ngroups; ++g) {
+    // Horner in ty over the members, whose powers of y run 0, 1, .., n - c:
+    // acc <- acc ty + coef tx^a Y_(a,b,c), taken from the largest b down.
+    float2 acc[F::E];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
+    const int cnt = gt.count[g];
+    for (int s = cnt - 1; s >= 0; --s) {
+      const int m = gt.grid[g][s];
+      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)z * N * Kx + kx;
+      float2 d[F::E];
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * Kx];
+      F::run(d, t, tw, T, slot);
+      const float fx = gt.coef[g][s] * ipow(tx, gt.a[g][s]);
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) {
+        acc[e].x = acc[e].x * tyv[e] + fx * d[e].x;
+        acc[e].y = acc[e].y * tyv[e] + fx * d[e].y;
+      }
+    }
+    float2* __restrict__ dst = H + (size_t)g * a.h_group_stride + regoff + (size_t)z * nslot * TK + c;
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+      const int ky = signed_freq<N>(F::out_index(t, e));
+      if (ky >= -M && ky <= M) dst[(size_t)(ky + M) * TK] = acc[e];
+    }
+  }
+}
+
+template <int N, int TK>
+static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s) {
+  YArgs a;
+  a.Kx = p.Kx;
+  a.x_grid_stride = (int64_t)p.N * p.N * p.Kx;
+  a.h_group_stride = (int64_t)p.H_group_stride;
+  a.gt = at<const GroupTable>(ws, p.off_tables);
+  a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
+  const size_t shmem = (size_t)TK * N * sizeof(float2);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shmem);
+  hipLaunchKernelGGL((ypass_kernel<N, TK>), dim3(p.nkt, N), dim3(TK * Fft<N>::T), shmem, s,
+                     at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// z pass with the contraction and the binning
+// ---------------------------------------------------------------------------------
+struct ZArgs {
+  int Kx;
+  int K2;          // K^2: modes with |n|^2 < K2 are binned
+  int dn;
+  int nbins;
+  int compensate;
+  int nkt;
+  int64_t h_group_stride;
+  int64_t n_items;
+  const TileTable* tt;
+};
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds NV per-lane values to bins[b][first .. first+NV) for the lanes with valid
+// bins: the wave first sums the lanes that share a bin, then one lane adds.
+template <int NV>
+__device__ __forceinline__ void wave_bin_add(double* bins, int b, bool valid, const double (&v)[NV], int first) {
+  if (blockDim.x < 64) {  // partial wave (tiny grids): plain LDS atomics
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) atomicAdd(&bins[b * kNumSums + first + j], v[j]);
+    }
+    return;
+  }
+  const int lo = wave_min_i(valid ? b : INT_MAX);
+  if (lo == INT_MAX) return;
+  const int hi = wave_max_i(valid ? b : -1);
+  const int lane = threadIdx.x & 63;
+  for (int bb = lo; bb <= hi; ++bb) {
+    const bool mine = valid && b == bb;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double s = wave_sum_d(mine ? v[j] : 0.0);
+      if (lane == 0) atomicAdd(&bins[bb * kNumSums + first + j], s);
+    }
+  }
+}
+
+__device__ __forceinline__ int isqrt_i(int n) {
+  int s = (int)sqrtf((float)n);
+  if (s * s > n) --s;
+  if ((s + 1) * (s + 1) <= n) ++s;
+  return s;
+}
+
+template <int N, int TK>
+__device__ __forceinline__ void zfft(const float2* __restrict__ col, int zstride, int c, int t, const float2* tw,
+                                     float2* T, float2 (&d)[Fft<N>::E]) {
+  using F = Fft<N>;
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) d[e] = col[(size_t)F::in_index(t, e) * zstride];
+  F::run(d, t, tw, T, ColSlot<TK>{c});
+}
+
+template <int N, int TK, int ELL>
+__global__ __launch_bounds__(TK * Fft<N>::T) void zpass_kernel(const float2* __restrict__ H, const float2* __restrict__ tw,
+                                                              const float* __restrict__ invw2,
+                                                              const float* __restrict__ alias,
+                                                              const double* __restrict__ scal, double* __restrict__ zpart,
+                                                              const ZArgs a) {
+  using F = Fft<N>;
+  extern __shared__ __align__(16) char smem[];
+  float2* T = reinterpret_cast<float2*>(smem);
+  double* bins = reinterpret_cast<double*>(smem + (size_t)TK * N * sizeof(float2));
+  const int tid = threadIdx.x;
+  const int c = tid % TK, t = tid / TK;
+  for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) bins[i] = 0.0;
+  const double S = scal[kNoiseS];
+  const float twoN = 2.0f / N;
+  int kzi[F::E];
+  float tzv[F::E];
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) {
+    kzi[e] = F::out_index(t, e);
+    tzv[e] = (float)signed_freq<N>(kzi[e]) * twoN;
+  }
+  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    int kt = 0;
+    for (int k = 1; k < a.nkt; ++k) kt = item >= a.tt->item0[k] ? k : kt;
+    const int M = a.tt->M[kt];
+    const int s = (int)(item - a.tt->item0[kt]);
+    const int ky = s - M;
+    const int kx = kt * TK + c;
+    const int zstride = (2 * M + 1) * TK;
+    const float2* base = H + a.tt->regoff[kt] + (size_t)s * TK + c;
+    const float tx = (float)kx * twoN, ty = (float)ky * twoN;
+    const float wxy = invw2[kx] * invw2[ky & (N - 1)];
+    const float cxy = alias[kx] * alias[ky & (N - 1)];
+    const int n2xy = kx * kx + ky * ky;
+    const double mu = kx == 0 ? 1.0 : 2.0;
+
+    float2 a0[F::E];
+    zfft<N, TK>(base, zstride, c, t, tw, T, a0);
+
+    float2 acc[F::E];
+    if (ELL >= 2) {
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
+      for (int cz = 2; cz >= 0; --cz) {  // Horner in tz: acc <- acc tz + FFT_z[H_(n,cz)]
+        float2 u[F::E];
+        zfft<N, TK>(base + (size_t)(1 + cz) * a.h_group_stride, zstride, c, t, tw, T, u);
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) {
+          acc[e].x = acc[e].x * tzv[e] + u[e].x;
+          acc[e].y = acc[e].y * tzv[e] + u[e].y;
+        }
+      }
+    }
+    // pass 1: counts, |n|, Q0, Q2 (ell_max >= 2) and the noise
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+      const int kz = signed_freq<N>(kzi[e]);
+      const int n2 = n2xy + kz * kz;
+      const bool valid = n2 > 0 && n2 < a.K2;
+      const int b = valid ? isqrt_i(n2) / a.dn : 0;
+      float iw = 1.0f, noise_f = 1.0f;
+      if (a.compensate >= 1) iw = wxy * invw2[kzi[e]];
+      if (a.compensate == 2) noise_f = cxy * alias[kzi[e]] * iw;
+      const float2 z0 = a0[e];
+      const float q0 = (z0.x * z0.x + z0.y * z0.y) * iw;
+      double w4[4];
+      w4[0] = mu;
+      w4[1] = mu * (double)sqrtf((float)n2);
+      w4[2] = mu * (double)q0;
+      w4[3] = 0.0;
+      if (ELL >= 2) {
+        const float tz = tzv[e];
+        const float inv_t2 = 1.0f / (tx * tx + ty * ty + tz * tz);
+        const float2 A2 = acc[e];
+        w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
+      }
+      // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise
+      wave_bin_add<4>(bins, b, valid, w4, 0);
+      double w1[1] = {mu * S * (double)noise_f};
+      wave_bin_add<1>(bins, b, valid, w1, 5);
+    }
+    if (ELL >= 4) {
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
+      for (int cz = 4; cz >= 0; --cz) {  // Horner in tz: acc <- acc tz + FFT_z[H_(n,cz)]
+        float2 u[F::E];
+        zfft<N, TK>(base + (size_t)(4 + cz) * a.h_group_stride, zstride, c, t, tw, T, u);
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) {
+          acc[e].x = acc[e].x * tzv[e] + u[e].x;
+          acc[e].y = acc[e].y * tzv[e] + u[e].y;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) {
+        const int kz = signed_freq<N>(kzi[e]);
+        const int n2 = n2xy + kz * kz;
+        const bool valid = n2 > 0 && n2 < a.K2;
+        const int b = valid ? isqrt_i(n2) / a.dn : 0;
+        const float iw = a.compensate >= 1 ? wxy * invw2[kzi[e]] : 1.0f;
+        const float tz = tzv[e];
+        const float t2 = tx * tx + ty * ty + tz * tz;
+        const float inv_t4 = 1.0f / (t2 * t2);
+        const float2 z0 = a0[e];
+        const float2 A4 = acc[e];
+        double w[1] = {mu * (double)((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw)};
+        wave_bin_add<1>(bins, b, valid, w, 4);
+      }
+    }
+  }
+  __syncthreads();
+  double* out = zpart + (size_t)blockIdx.x * a.nbins * kNumSums;
+  for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) out[i] = bins[i];
+}
+
+template <int N, int TK, int ELL>
+static hipError_t launch_z3(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
+  const size_t shmem = (size_t)TK * N * sizeof(float2) + (size_t)p.nbins * kNumSums * sizeof(double);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  hipLaunchKernelGGL((zpass_kernel<N, TK, ELL>), dim3(p.z_blocks), dim3(TK * Fft<N>::T), shmem, s,
+                     at<const float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), at<const float>(ws, p.off_invw2),
+                     at<const float>(ws, p.off_alias), at<const double>(ws, p.off_scalars),
+                     at<double>(ws, p.off_zpart), a);
+  return hipGetLastError();
+}
+
+template <int N, int TK>
+static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
+  ZArgs a;
+  a.Kx = p.Kx;
+  a.K2 = p.K * p.K;
+  a.dn = p.dn;
+  a.nbins = p.nbins;
+  a.compensate = p.compensate;
+  a.nkt = p.nkt;
+  a.h_group_stride = (int64_t)p.H_group_stride;
+  a.n_items = p.z_items;
+  a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
+  switch (p.ell_max) {
+    case 0: return launch_z3<N, TK, 0>(p, ws, a, s);
+    case 2: return launch_z3<N, TK, 2>(p, ws, a, s);
+    default: return launch_z3<N, TK, 4>(p, ws, a, s);
+  }
+}
+
+
+
+hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s) {
+  switch (p.N) {
+    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s);
+    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s);
+    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s);
+    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s);
+    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s);
+    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s);
+    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s);
+    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_zpass(const Plan& p, char* ws, hipStream_t s) {
+  switch (p.N) {
+    case 8: return launch_z2<8, tile_cols<8>()>(p, ws, s);
+    case 16: return launch_z2<16, tile_cols<16>()>(p, ws, s);
+    case 32: return launch_z2<32, tile_cols<32>()>(p, ws, s);
+    case 64: return launch_z2<64, tile_cols<64>()>(p, ws, s);
+    case 128: return launch_z2<128, tile_cols<128>()>(p, ws, s);
+    case 256: return launch_z2<256, tile_cols<256>()>(p, ws, s);
+    case 512: return launch_z2<512, tile_cols<512>()>(p, ws, s);
+    case 1024: return launch_z2<1024, tile_cols<1024>()>(p, ws, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pk

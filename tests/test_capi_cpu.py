@@ -1,0 +1,80 @@
+"""CPU checks of the C interface: the library loads, exports every symbol of
+include/pk.h, and its host-side logic (configuration checks, workspace sizing,
+monomial table) behaves; nothing here launches a kernel."""
+import os
+import re
+
+import pytest
+
+from paper_1505_05341_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pk_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = native.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_monomial_table_matches_degrees():
+    assert [native.num_grids(e) for e in (0, 2, 4)] == [1, 7, 22]
+    monos = [native.monomial(m) for m in range(22)]
+    assert len(set(monos)) == 22
+    assert [sum(m) for m in monos] == [0] + [2] * 6 + [4] * 15
+
+
+def cfg(**kw):
+    d = dict(N=64, box_min=(0.0, 0.0, 0.0), L=100.0, dn=1, nbins=32)
+    d.update(kw)
+    return d
+
+
+def test_workspace_size_grows_with_particles_and_grid():
+    a = native.workspace_size(cfg(), 10, 100)
+    b = native.workspace_size(cfg(), 10, 100000)
+    c = native.workspace_size(cfg(N=128, nbins=64), 10, 100)
+    assert b - a >= 16 * (100000 - 100)
+    assert c > a
+    assert a % 256 == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=48), -6), (dict(N=2048, nbins=8), -6), (dict(ell_max=3), -1), (dict(assign=1), -1),
+    (dict(los=2), -1), (dict(compensate=3), -1), (dict(dn=0), -1), (dict(nbins=33), -1),
+    (dict(nbins=0), -1), (dict(L=-1.0), -1), (dict(norm_from=2), -1),
+])
+def test_bad_configurations(kw, code):
+    c = native.make_config(cfg(**kw))
+    if kw.get("nbins") == 0:
+        c.nbins = 0
+    import ctypes
+    out = ctypes.c_size_t()
+    st = native.load().pk_workspace_size(ctypes.byref(c), 1, 1, ctypes.byref(out))
+    assert st == code, native.last_error()
+
+
+def test_negative_sizes_and_too_many_particles():
+    with pytest.raises(native.PkError) as e:
+        native.workspace_size(cfg(), -1, 5)
+    assert e.value.status == -1
+    with pytest.raises(native.PkError) as e:
+        native.workspace_size(cfg(), 2 ** 30, 2 ** 30)
+    assert e.value.status == -6
+
+
+def test_status_strings_and_result_size():
+    lib = native.load()
+    assert lib.pk_status_string(0) == b"ok"
+    assert lib.pk_status_string(-4) == b"workspace too small"
+    c = native.make_config(cfg())
+    import ctypes
+    assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 6 + 4
