@@ -125,6 +125,27 @@ pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const
                               void* workspace, size_t workspace_bytes, double* d_result,
                               void* hip_stream);
 
+/* Batched estimator for ensembles of mocks (many catalogues of uneven size, each with
+ * its own configuration). Mocks are processed in order over `lanes` (1 or 2) internal
+ * HIP streams, each with its own slice of the workspace, so that one mock's short
+ * kernels overlap another's transforms. Each mock's stages are captured into a hipGraph;
+ * mocks of the same size class (N, assign, ell_max, nbins, dn, los, compensate) reuse
+ * the instantiated graph of their lane. Work starts after everything already queued on
+ * `hip_stream` and the call returns after all mocks are done.
+ *   cfgs, gals, rans  arrays of n_mocks configurations and device catalogues
+ *   workspace         device memory of pk_workspace_size_batch() bytes for the same
+ *                     arguments and lanes, 256-byte aligned
+ *   outs              n_mocks result structs (host arrays as for pk_multipoles)
+ *   per_mock          n_mocks statuses (PK_OK or the mock's error; outs[i] is untouched
+ *                     when per_mock[i] != PK_OK)
+ * Returns PK_OK when every mock was run (per-mock input errors are reported in
+ * per_mock), or the first argument / device error. */
+pk_status pk_workspace_size_batch(const pk_config* cfgs, const pk_catalog* gals, const pk_catalog* rans,
+                                  int32_t n_mocks, int32_t lanes, size_t* bytes);
+pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, const pk_catalog* rans,
+                              int32_t n_mocks, int32_t lanes, void* workspace, size_t workspace_bytes,
+                              pk_result* outs, pk_status* per_mock, void* hip_stream);
+
 /* Number of doubles pk_multipoles_async writes. */
 int64_t pk_result_doubles(const pk_config* cfg);
 

@@ -5,4 +5,5 @@ Gil-Marin, Ruggeri & Percival (2015). The C interface is include/pk.h (libpk.so)
 this package is its Python binding plus the seeded synthetic catalogue generators.
 """
 from .native import PkError, load  # noqa: F401
-from .api import DeviceCatalog, Workspace, pk_multipoles, stage_xgrids, xgrid_view  # noqa: F401
+from .api import (DeviceCatalog, Workspace, pk_multipoles, pk_multipoles_batch, stage_xgrids,  # noqa: F401
+                  xgrid_view)

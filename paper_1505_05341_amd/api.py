@@ -91,6 +91,49 @@ def pk_multipoles(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: 
     return _result_dict(c, k, P, noise, nm, res)
 
 
+def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace | None = None, stream=None):
+    """Batched estimator over lists of device catalogues and configurations.
+
+    Returns (results, statuses): one result dict per mock (None where its status is not
+    PK_OK) and the per-mock status codes."""
+    lib = native.load()
+    n = len(cfgs)
+    if not (len(gals) == len(rans) == n):
+        raise ValueError("gals, rans and cfgs must have the same length")
+    CfgArr = native.PkConfig * max(n, 1)
+    CatArr = native.PkCatalog * max(n, 1)
+    carr = CfgArr(*[native.make_config(c) for c in cfgs])
+    garr = CatArr(*[g.c_struct() for g in gals])
+    rarr = CatArr(*[r.c_struct() for r in rans])
+    nbytes = ctypes.c_size_t()
+    native.check(lib.pk_workspace_size_batch(carr, garr, rarr, n, lanes, ctypes.byref(nbytes)))
+    ws = (workspace or Workspace()).get(int(nbytes.value))
+    outs = (native.PkResult * max(n, 1))()
+    keep = []
+    dp = ctypes.POINTER(ctypes.c_double)
+    for i in range(n):
+        c = carr[i]
+        nb, nl = c.nbins, c.ell_max // 2 + 1
+        k, P, noise, nm = np.zeros(nb), np.zeros(nb * nl), np.zeros(nb), np.zeros(nb, dtype=np.int64)
+        keep.append((k, P, noise, nm))
+        outs[i].k_eff = k.ctypes.data_as(dp)
+        outs[i].P = P.ctypes.data_as(dp)
+        outs[i].noise = noise.ctypes.data_as(dp)
+        outs[i].nmodes = nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    status = (ctypes.c_int32 * max(n, 1))()
+    s = stream if stream is not None else native.current_stream()
+    native.check(lib.pk_multipoles_batch(carr, garr, rarr, n, lanes, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         outs, status, s))
+    results = []
+    for i in range(n):
+        if status[i] != native.PK_OK:
+            results.append(None)
+            continue
+        k, P, noise, nm = keep[i]
+        results.append(_result_dict(carr[i], k, P, noise, nm, outs[i]))
+    return results, [int(status[i]) for i in range(n)]
+
+
 def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
     """Runs up to the fused assignment + x transform and returns (workspace tensor, layout),
     layout[m] = (byte offset, kx_count) of grid m (complex64 X[z][y][kx])."""

@@ -129,9 +129,10 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_invw2 = take(sizeof(float) * p.N);
   p.off_alias = take(sizeof(float) * p.N);
   p.off_tables = take(sizeof(GroupTable) + sizeof(TileTable));
-  p.off_rowcnt = take(sizeof(uint32_t) * nrow);
+  p.off_rowcnt = take(sizeof(uint32_t) * ((size_t)p.N * sort_blocks(n_gal + n_ran) + 1));  // plane histograms
   p.off_rowoff = take(sizeof(uint32_t) * (nrow + 1));
   p.off_blocksum = take(sizeof(uint32_t) * 1024);
+  p.off_tmp = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_X = take(sizeof(float) * 2 * (size_t)p.G * nrow * p.Kx);
   p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);
@@ -286,6 +287,170 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
   out->alpha = tail[0];
   out->I = tail[1];
   out->S = tail[2];
+  return PK_OK;
+}
+
+// ------------------------------------------------------------------------- batches
+
+static pk_status batch_layout(const pk_config* cfgs, const pk_catalog* gals, const pk_catalog* rans, int32_t n,
+                              int32_t lanes, size_t* lane_bytes, int64_t* rd_max, size_t* total) {
+  if (!cfgs || !gals || !rans) return fail(PK_EINVAL, "null batch array");
+  if (n < 0) return fail(PK_EINVAL, "n_mocks < 0");
+  if (lanes < 1 || lanes > 2) return fail(PK_EINVAL, "lanes must be 1 or 2");
+  size_t wmax = 256;
+  int64_t rmax = 1;
+  for (int32_t i = 0; i < n; ++i) {
+    Plan p;
+    const char* why;
+    pk_status st = check_catalog(&gals[i], cfgs[i].norm_from == 1, "galaxy");
+    if (st == PK_OK) st = check_catalog(&rans[i], cfgs[i].norm_from == 0, "random");
+    if (st == PK_OK) st = make_plan(&cfgs[i], gals[i].n, rans[i].n, &p, &why);
+    if (st != PK_OK) return fail(st, "mock " + std::to_string(i) + ": " + g_last_error);
+    if (p.total > wmax) wmax = p.total;
+    if (p.result_doubles > rmax) rmax = p.result_doubles;
+  }
+  *lane_bytes = align256(wmax);
+  *rd_max = rmax;
+  *total = (size_t)lanes * *lane_bytes + align256(sizeof(double) * (size_t)rmax * (n > 0 ? n : 1));
+  return PK_OK;
+}
+
+struct GraphSlot {
+  bool valid = false;
+  int key[8] = {0};
+  hipGraphExec_t exec = nullptr;
+};
+
+static void class_key(const Plan& p, int (&k)[8]) {
+  k[0] = p.N; k[1] = p.assign; k[2] = p.ell_max; k[3] = p.nbins; k[4] = p.dn; k[5] = p.los; k[6] = p.compensate;
+  k[7] = p.norm_from;
+}
+
+}  // extern "C"
+
+static pk_status batch_fail_cleanup(pk_status st, hipStream_t* ls, int lanes, GraphSlot* gs, hipEvent_t* ev, int nev) {
+  for (int l = 0; l < lanes; ++l) {
+    if (gs[l].exec) hipGraphExecDestroy(gs[l].exec);
+    if (ls[l]) hipStreamDestroy(ls[l]);
+  }
+  for (int i = 0; i < nev; ++i)
+    if (ev[i]) hipEventDestroy(ev[i]);
+  return st;
+}
+
+extern "C" {
+
+pk_status pk_workspace_size_batch(const pk_config* cfgs, const pk_catalog* gals, const pk_catalog* rans,
+                                  int32_t n_mocks, int32_t lanes, size_t* bytes) {
+  if (!bytes) return fail(PK_EINVAL, "null bytes pointer");
+  size_t lane_bytes, total;
+  int64_t rd;
+  const pk_status st = batch_layout(cfgs, gals, rans, n_mocks, lanes, &lane_bytes, &rd, &total);
+  if (st == PK_OK) *bytes = total;
+  return st;
+}
+
+pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, const pk_catalog* rans, int32_t n_mocks,
+                              int32_t lanes, void* workspace, size_t workspace_bytes, pk_result* outs,
+                              pk_status* per_mock, void* hip_stream) {
+  size_t lane_bytes, total;
+  int64_t rd;
+  pk_status st = batch_layout(cfgs, gals, rans, n_mocks, lanes, &lane_bytes, &rd, &total);
+  if (st != PK_OK) return st;
+  if (!outs || !per_mock) return fail(PK_EINVAL, "null outs or per_mock");
+  if (!workspace || workspace_bytes < total)
+    return fail(PK_EWORKSPACE, "batch workspace needs " + std::to_string(total) + " bytes");
+  if (((uintptr_t)workspace & 255) != 0) return fail(PK_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (n_mocks == 0) return PK_OK;
+  char* ws = static_cast<char*>(workspace);
+  double* d_res = at<double>(ws, (size_t)lanes * lane_bytes);
+  hipStream_t caller = (hipStream_t)hip_stream;
+  hipStream_t ls[2] = {nullptr, nullptr};
+  GraphSlot gs[2];
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipError_t e;
+  for (int i = 0; i < 3; ++i)
+    if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess)
+      return batch_fail_cleanup(hip_fail(e, "event create"), ls, lanes, gs, ev, 3);
+  for (int l = 0; l < lanes; ++l)
+    if ((e = hipStreamCreateWithFlags(&ls[l], hipStreamNonBlocking)) != hipSuccess)
+      return batch_fail_cleanup(hip_fail(e, "stream create"), ls, lanes, gs, ev, 3);
+  // lanes start after the caller's queued work
+  if ((e = hipEventRecord(ev[0], caller)) != hipSuccess) return batch_fail_cleanup(hip_fail(e, "record"), ls, lanes, gs, ev, 3);
+  for (int l = 0; l < lanes; ++l) hipStreamWaitEvent(ls[l], ev[0], 0);
+  const bool timing = g_timing.enabled;
+  g_timing.enabled = false;  // no per-stage events inside captured graphs
+  for (int32_t i = 0; i < n_mocks; ++i) {
+    const int l = i % lanes;
+    Plan p;
+    const char* why;
+    make_plan(&cfgs[i], gals[i].n, rans[i].n, &p, &why);
+    char* lws = ws + (size_t)l * lane_bytes;
+    hipGraph_t graph = nullptr;
+    if ((e = hipStreamBeginCapture(ls[l], hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+      g_timing.enabled = timing;
+      return batch_fail_cleanup(hip_fail(e, "begin capture"), ls, lanes, gs, ev, 3);
+    }
+    st = run_stages(p, gals[i], rans[i], lws, d_res + (size_t)i * rd, ls[l], false);
+    e = hipStreamEndCapture(ls[l], &graph);
+    if (st != PK_OK || e != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      g_timing.enabled = timing;
+      return batch_fail_cleanup(st != PK_OK ? st : hip_fail(e, "end capture"), ls, lanes, gs, ev, 3);
+    }
+    int key[8];
+    class_key(p, key);
+    bool reused = false;
+    if (gs[l].valid && memcmp(gs[l].key, key, sizeof(key)) == 0) {
+      hipGraphExecUpdateResult res;
+      hipGraphNode_t bad = nullptr;
+      reused = hipGraphExecUpdate(gs[l].exec, graph, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+    }
+    if (!reused) {
+      if (gs[l].exec) hipGraphExecDestroy(gs[l].exec);
+      gs[l].exec = nullptr;
+      gs[l].valid = false;
+      if ((e = hipGraphInstantiate(&gs[l].exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        hipGraphDestroy(graph);
+        g_timing.enabled = timing;
+        return batch_fail_cleanup(hip_fail(e, "graph instantiate"), ls, lanes, gs, ev, 3);
+      }
+      memcpy(gs[l].key, key, sizeof(key));
+      gs[l].valid = true;
+    }
+    hipGraphDestroy(graph);
+    if ((e = hipGraphLaunch(gs[l].exec, ls[l])) != hipSuccess) {
+      g_timing.enabled = timing;
+      return batch_fail_cleanup(hip_fail(e, "graph launch"), ls, lanes, gs, ev, 3);
+    }
+  }
+  g_timing.enabled = timing;
+  // the caller's stream waits for every lane
+  for (int l = 0; l < lanes; ++l) {
+    hipEventRecord(ev[1 + l], ls[l]);
+    hipStreamWaitEvent(caller, ev[1 + l], 0);
+  }
+  std::vector<double> h((size_t)rd * n_mocks);
+  e = hipMemcpyAsync(h.data(), d_res, sizeof(double) * h.size(), hipMemcpyDeviceToHost, caller);
+  if (e == hipSuccess) e = hipStreamSynchronize(caller);
+  if (e != hipSuccess) return batch_fail_cleanup(hip_fail(e, "batch results"), ls, lanes, gs, ev, 3);
+  batch_fail_cleanup(PK_OK, ls, lanes, gs, ev, 3);
+  for (int32_t i = 0; i < n_mocks; ++i) {
+    const int nb = cfgs[i].nbins, nl = cfgs[i].ell_max / 2 + 1;
+    const double* r = h.data() + (size_t)i * rd;
+    const double* tail = r + (size_t)nb * (3 + nl);
+    per_mock[i] = flags_status((int)tail[3]);
+    if (per_mock[i] != PK_OK) continue;
+    pk_result* o = &outs[i];
+    if (o->k_eff) memcpy(o->k_eff, r, sizeof(double) * nb);
+    if (o->P) memcpy(o->P, r + nb, sizeof(double) * nb * nl);
+    if (o->noise) memcpy(o->noise, r + (size_t)nb * (1 + nl), sizeof(double) * nb);
+    if (o->nmodes)
+      for (int b = 0; b < nb; ++b) o->nmodes[b] = (int64_t)r[(size_t)nb * (2 + nl) + b];
+    o->alpha = tail[0];
+    o->I = tail[1];
+    o->S = tail[2];
+  }
   return PK_OK;
 }
 

@@ -14,7 +14,8 @@ constexpr int kMaxGroups = 9;
 constexpr int kMaxMembers = 5;
 constexpr int kMaxTiles = 64;       // kx tiles of 16 columns up to N = 2048
 constexpr int kStatsBlocks = 512;   // blocks of the catalogue-scalar reduction
-constexpr int kScanChunk = 4096;    // row counters per scan block
+constexpr int kScanChunk = 4096;    // counters per scan block
+constexpr int kSortBlocks = 2048;   // level-A sort blocks (one contiguous particle range each)
 constexpr int kNumSums = 6;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise
 
 // Device scalars written by the catalogue-scalar kernels.
@@ -86,12 +87,13 @@ struct Plan {
   TileTable tiles;
   // workspace offsets (bytes)
   size_t off_scalars, off_partials, off_flags, off_tw, off_invw2, off_alias, off_tables;
-  size_t off_rowcnt, off_rowoff, off_blocksum, off_sorted, off_X, off_H, off_zpart, off_result;
+  size_t off_rowcnt, off_rowoff, off_blocksum, off_tmp, off_sorted, off_X, off_H, off_zpart, off_result;
   size_t total;
   size_t H_group_stride;   // float2 elements per group in H
   int64_t result_doubles;
 };
 
+int sort_blocks(int64_t ntot);
 pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* plan, const char** why);
 
 // Launchers (queued on `s`; they return the launch error, if any).

@@ -2,14 +2,20 @@
 // Sec. 4 for the assignment).
 //
 // One block owns one target grid row (y, z) for a group of the 1, 7 or 22 monomial
-// grids F rhat^m. It reads the particles of the source rows whose stencil reaches
-// (y, z) -- rows were made contiguous by the counting sort -- and for each particle
-// computes its own line of sight rhat = (x - observer)/|x - observer|, the monomials
-// rhat^m, and adds w' W(x) rhat^m into an LDS copy of the row of every grid with LDS
-// atomics. The finished rows never go to HBM in real space: two real rows are packed
-// as one complex row, transformed along x in registers and LDS, separated into their
-// two half spectra, and only kx < Kx is written (every mode with |kx| >= Kx lies
-// outside the binned sphere).
+// grids F rhat^m. The particles whose stencil reaches the row are those of a few
+// source rows, which the counting sort made contiguous. They are processed in chunks:
+//   1. each particle's own line of sight rhat = (x - observer)/|x - observer|, its
+//      base cell along x, its x offset and its weight w' W_y W_z go to LDS;
+//   2. the chunk is counting-sorted by base cell in LDS (integer atomics only);
+//   3. each thread owns target cells and gathers, from the particles of the 2 (CIC)
+//      or 3 (TSC) source cells that reach it, w' W rhat^m for every grid of the block,
+//      summing in registers.
+// No floating-point atomics are used: on gfx950 LDS float atomics run several times
+// slower than integer ones, and a scatter would need one per particle, cell and grid.
+// The finished rows never go to HBM in real space: two real rows are packed as one
+// complex row, transformed along x in registers and LDS, separated into their two half
+// spectra, and only kx < Kx is written (every mode with |kx| >= Kx lies outside the
+// binned sphere).
 #include <hip/hip_runtime.h>
 
 #include "fft_dev.hpp"
@@ -43,32 +49,157 @@ __device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&
   m[17] = yy * yy; m[18] = yy * yz; m[19] = yy * zz; m[20] = yz * zz; m[21] = zz * zz;
 }
 
-template <int N, int ASSIGN, int G, int G0, int NG>
-__device__ __forceinline__ void deposit(float* __restrict__ rows, const float4 q, int oy, int oz, const XArgs& a) {
-  constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
+constexpr int XTHREADS = 512;
+constexpr int XCHUNK = 1024;   // particles per LDS chunk
+
+// Bytes of the gather-phase LDS area: pa float4[XCHUNK] (fx, w' W_y W_z, rx, ry),
+// pr float[XCHUNK] (rz), pix uint16[XCHUNK] (base cell), perm uint16[XCHUNK],
+// cnt uint32[N] (counts, then cursors), st uint32[N + 1] (first particle of each cell).
+template <int N>
+constexpr size_t gather_lds_bytes() {
+  return (size_t)XCHUNK * (16 + 4 + 2 + 2) + (size_t)N * 4 + (size_t)(N + 1) * 4;
+}
+
+// Exclusive scan of cnt[0, N) into st[0, N] (st[N] = total); cnt[i] = st[i] on exit.
+template <int N>
+__device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
+  constexpr int PER = (N + XTHREADS - 1) / XTHREADS;
+  __shared__ uint32_t wsum[XTHREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t v[PER];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = tid * PER + j;
+    v[j] = idx < N ? cnt[idx] : 0u;
+    loc += v[j];
+  }
+  uint32_t inc = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t ex = inc - loc;
+  for (int w = 0; w < wv; ++w) ex += wsum[w];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = tid * PER + j;
+    if (idx < N) {
+      st[idx] = ex;
+      cnt[idx] = ex;
+    }
+    ex += v[j];
+  }
+  if (tid == XTHREADS - 1) st[N] = ex;
+  __syncthreads();
+}
+
+// Gathers rows G0 .. G0+NG of the block's target row into LDS rows[g - G0][x]
+// (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
+template <int N, int ASSIGN, int G, int G0, int NG, int NP, int S = (ASSIGN == PK_CIC ? 2 : 3)>
+__device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict__ sorted, const uint32_t (&beg)[S * S],
+                                            const uint32_t (&pre)[S * S + 1], const XArgs& a) {
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
-  const float uy = grid_coord(q.y, a.bmin[1], a.invH);
-  const float uz = grid_coord(q.z, a.bmin[2], a.invH);
-  const float ux = grid_coord(q.x, a.bmin[0], a.invH);
-  const float wyz = q.w * stencil_weight<ASSIGN>(base_offset<ASSIGN>(uy), oy) *
-                    stencil_weight<ASSIGN>(base_offset<ASSIGN>(uz), oz);
-  const int ix = base_index<ASSIGN>(ux, N);
-  const float fx = base_offset<ASSIGN>(ux);
-  float rx = 0.0f, ry = 0.0f, rz = 1.0f;
-  if (a.los == 0) {
-    const float dx = q.x - a.obs[0], dy = q.y - a.obs[1], dz = q.z - a.obs[2];
-    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-    rx = dx * inv; ry = dy * inv; rz = dz * inv;
-  }
-  float m[G];
-  monomials<G>(rx, ry, rz, m);
+  constexpr int CPT = (N + XTHREADS - 1) / XTHREADS;  // target cells per thread
+  char* base = reinterpret_cast<char*>(lds);
+  float4* pa = reinterpret_cast<float4*>(base);
+  float* pr = reinterpret_cast<float*>(base + XCHUNK * 16);
+  uint16_t* pix = reinterpret_cast<uint16_t*>(base + XCHUNK * 20);
+  uint16_t* perm = reinterpret_cast<uint16_t*>(base + XCHUNK * 22);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + XCHUNK * 24);
+  uint32_t* st = cnt + N;
+  const int tid = threadIdx.x;
+  float acc[CPT][NG];
 #pragma unroll
-  for (int o = 0; o < S; ++o) {
-    const int cell = (ix + O0 + o) & (N - 1);
-    const float v = wyz * stencil_weight<ASSIGN>(fx, O0 + o);
+  for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int g = 0; g < NG; ++g) atomicAdd(&rows[g * N + cell], v * m[G0 + g]);
+    for (int g = 0; g < NG; ++g) acc[c][g] = 0.0f;
+  for (int i = tid; i < N; i += XTHREADS) cnt[i] = 0u;
+  __syncthreads();
+  const uint32_t total = pre[S * S];
+  for (uint32_t c0 = 0; c0 < total; c0 += XCHUNK) {
+    const int n = (int)(total - c0 < (uint32_t)XCHUNK ? total - c0 : (uint32_t)XCHUNK);
+    // 1. per-particle values
+    for (int i = tid; i < n; i += XTHREADS) {
+      const uint32_t f = c0 + i;
+      int s = 0;
+      uint32_t b0 = beg[0], p0 = 0;
+#pragma unroll
+      for (int k = 1; k < S * S; ++k) {
+        if (f >= pre[k]) {
+          s = k;
+          b0 = beg[k];
+          p0 = pre[k];
+        }
+      }
+      const float4 q = sorted[b0 + (f - p0)];
+      const int oy = O0 + s % S, oz = O0 + s / S;
+      const float uy = grid_coord(q.y, a.bmin[1], a.invH);
+      const float uz = grid_coord(q.z, a.bmin[2], a.invH);
+      const float ux = grid_coord(q.x, a.bmin[0], a.invH);
+      const float wyz = q.w * stencil_weight<ASSIGN>(base_offset<ASSIGN>(uy), oy) *
+                        stencil_weight<ASSIGN>(base_offset<ASSIGN>(uz), oz);
+      const int ix = base_index<ASSIGN>(ux, N);
+      float rx = 0.0f, ry = 0.0f, rz = 1.0f;
+      if (a.los == 0) {
+        const float dx = q.x - a.obs[0], dy = q.y - a.obs[1], dz = q.z - a.obs[2];
+        const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        rx = dx * inv;
+        ry = dy * inv;
+        rz = dz * inv;
+      }
+      pa[i] = make_float4(base_offset<ASSIGN>(ux), wyz, rx, ry);
+      pr[i] = rz;
+      pix[i] = (uint16_t)ix;
+      atomicAdd(&cnt[ix], 1u);
+    }
+    __syncthreads();
+    // 2. counting sort of the chunk by base cell
+    scan_counts<N>(cnt, st);
+    for (int i = tid; i < n; i += XTHREADS) {
+      const uint32_t pos = atomicAdd(&cnt[pix[i]], 1u);
+      perm[pos] = (uint16_t)i;
+    }
+    __syncthreads();
+    // 3. gather: target cell x receives from base cells x - O0 - o with stencil offset O0 + o
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int x = tid + c * XTHREADS;
+      if (x < N) {
+#pragma unroll
+        for (int o = 0; o < S; ++o) {
+          const int sc = (x - O0 - o) & (N - 1);
+          const uint32_t k1 = st[sc + 1];
+          for (uint32_t k = st[sc]; k < k1; ++k) {
+            const int i = perm[k];
+            const float4 p = pa[i];
+            const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
+            float m[G];
+            monomials<G>(p.z, p.w, pr[i], m);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) acc[c][g] += w * m[G0 + g];
+          }
+        }
+        cnt[x] = 0u;  // ready for the next chunk (only this thread touches cell x here)
+      }
+    }
+    __syncthreads();
   }
+  // rows alias the gather area: all gathers are done (barrier above)
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int x = tid + c * XTHREADS;
+    if (x < N) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) lds[g * N + x] = acc[c][g];
+#pragma unroll
+      for (int g = NG; g < 2 * NP; ++g) lds[g * N + x] = 0.0f;
+    }
+  }
+  __syncthreads();
 }
 
 // LDS slot of index i of one transform: an XOR swizzle inside each block of 16
@@ -76,8 +207,6 @@ __device__ __forceinline__ void deposit(float* __restrict__ rows, const float4 q
 struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
-
-constexpr int XTHREADS = 512;
 
 template <int N, int ASSIGN, int ELL, int SPLIT>
 __global__ __launch_bounds__(XTHREADS) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
@@ -95,8 +224,6 @@ __global__ __launch_bounds__(XTHREADS) void xpass_kernel(const float4* __restric
   const int g0 = part * GB;
   const int ng = G - g0 < GB ? G - g0 : GB;
 
-  for (int i = tid; i < 2 * NP * N; i += blockDim.x) lds[i] = 0.0f;
-
   // source rows: the particles whose base cell (iy, iz) = (y - oy, z - oz) reach this row
   uint32_t beg[S * S], pre[S * S + 1];
   pre[0] = 0;
@@ -108,30 +235,13 @@ __global__ __launch_bounds__(XTHREADS) void xpass_kernel(const float4* __restric
     beg[s] = rowoff[r];
     pre[s + 1] = pre[s] + (rowoff[r + 1] - beg[s]);
   }
-  __syncthreads();
-  const uint32_t total = pre[S * S];
-  for (uint32_t f = tid; f < total; f += blockDim.x) {
-    int s = 0;
-    uint32_t b0 = beg[0], p0 = 0;
-#pragma unroll
-    for (int k = 1; k < S * S; ++k) {
-      if (f >= pre[k]) {
-        s = k;
-        b0 = beg[k];
-        p0 = pre[k];
-      }
-    }
-    const float4 q = sorted[b0 + (f - p0)];
-    const int oy = O0 + s % S, oz = O0 + s / S;
-    if (SPLIT == 1) {
-      deposit<N, ASSIGN, G, 0, G>(lds, q, oy, oz, a);
-    } else if (part == 0) {
-      deposit<N, ASSIGN, G, 0, GB>(lds, q, oy, oz, a);
-    } else {
-      deposit<N, ASSIGN, G, GB, G - GB>(lds, q, oy, oz, a);
-    }
+  if (SPLIT == 1) {
+    gather_rows<N, ASSIGN, G, 0, G, NP>(lds, sorted, beg, pre, a);
+  } else if (part == 0) {
+    gather_rows<N, ASSIGN, G, 0, GB, NP>(lds, sorted, beg, pre, a);
+  } else {
+    gather_rows<N, ASSIGN, G, GB, G - GB, NP>(lds, sorted, beg, pre, a);
   }
-  __syncthreads();
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
   const int npairs = (ng + 1) / 2;
@@ -176,7 +286,8 @@ static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t
   constexpr int SPLIT = (N >= 1024 && G > 16) ? 2 : 1;
   constexpr int GB = (G + SPLIT - 1) / SPLIT;
   constexpr int NP = (GB + 1) / 2;
-  const size_t shmem = (size_t)2 * NP * N * sizeof(float);
+  const size_t rows = (size_t)2 * NP * N * sizeof(float);
+  const size_t shmem = rows > gather_lds_bytes<N>() ? rows : gather_lds_bytes<N>();
   hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, N, SPLIT), dim3(XTHREADS), shmem, s,
                      at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
                      at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);

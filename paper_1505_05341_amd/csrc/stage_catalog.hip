@@ -14,11 +14,8 @@ namespace pk {
 // Workspace initialisation: flags, row counters, the FFT twiddle table and the
 // per-axis window tables, all computed here in FP64 and stored as FP32.
 // --------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void init_kernel(int N, int assign, int* flags, uint32_t* rowcnt,
-                                                   float2* tw, float* invw2, float* alias) {
-  const int64_t nrow = (int64_t)N * N;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += stride) rowcnt[i] = 0u;
+__global__ __launch_bounds__(256) void init_kernel(int N, int assign, int* flags, float2* tw, float* invw2,
+                                                   float* alias) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) *flags = 0;
   if (t < N) {
@@ -54,13 +51,9 @@ hipError_t launch_init(const Plan& p, char* ws, hipStream_t s) {
   memcpy(&words, &p.groups, sizeof(GroupTable));
   memcpy(reinterpret_cast<char*>(&words) + sizeof(GroupTable), &p.tiles, sizeof(TileTable));
   hipLaunchKernelGGL(copy_tables_kernel, dim3(1), dim3(256), 0, s, words, at<uint32_t>(ws, p.off_tables));
-  const int64_t nrow = (int64_t)p.N * p.N;
-  int blocks = (int)((nrow + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  if (blocks * 256 < p.N) blocks = (p.N + 255) / 256;
+  const int blocks = (p.N + 255) / 256;
   hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, p.N, p.assign, at<int>(ws, p.off_flags),
-                     at<uint32_t>(ws, p.off_rowcnt), at<float2>(ws, p.off_tw), at<float>(ws, p.off_invw2),
-                     at<float>(ws, p.off_alias));
+                     at<float2>(ws, p.off_tw), at<float>(ws, p.off_invw2), at<float>(ws, p.off_alias));
   return hipGetLastError();
 }
 
@@ -147,9 +140,11 @@ hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& 
 }
 
 // --------------------------------------------------------------------------------
-// Counting sort of the particles by grid row (y, z): histogram, exclusive scan,
-// scatter of (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1).
-// Invalid particles are flagged and left out; the host turns a flag into an error.
+// Counting sort of the particles by grid row (y, z), in two privatised levels so that
+// no device-scope atomics are needed: level A sorts by z plane with per-block LDS
+// histograms, level B sorts each plane by row y in one block. The payload is
+// (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1). Invalid
+// particles are flagged and left out; the host turns a flag into an error.
 // --------------------------------------------------------------------------------
 struct SortGeom {
   float bmin[3];
@@ -183,37 +178,106 @@ __device__ __forceinline__ bool valid_particle(const SortGeom& g, float x, float
   return true;
 }
 
+// Level A, pass 1: per-block histogram over z planes in LDS, stored plane-major
+// (ph[plane * B + block]) so that one exclusive scan gives every block's first slot in
+// every plane. Each block owns the contiguous particle range [blk * per, (blk+1) * per).
 template <int ASSIGN>
-__global__ __launch_bounds__(256) void hist_kernel(pk_catalog gal, pk_catalog ran, SortGeom g, uint32_t* rowcnt,
-                                                   int* flags) {
+__global__ __launch_bounds__(256) void plane_hist_kernel(pk_catalog gal, pk_catalog ran, SortGeom g, int64_t per,
+                                                         uint32_t* ph, int* flags) {
+  extern __shared__ uint32_t h[];
+  for (int i = threadIdx.x; i < g.N; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
   const int64_t ntot = gal.n + ran.n;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < ntot ? i0 + per : ntot;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const float* q = i < gal.n ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
     const float x = q[0], y = q[1], z = q[2];
     if (!valid_particle<true>(g, x, y, z, flags)) continue;
-    const int iy = base_index<ASSIGN>(grid_coord(y, g.bmin[1], g.invH), g.N);
-    const int iz = base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N);
-    atomicAdd(&rowcnt[(int64_t)iz * g.N + iy], 1u);
+    atomicAdd(&h[base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N)], 1u);
   }
+  __syncthreads();
+  for (int pl = threadIdx.x; pl < g.N; pl += blockDim.x) ph[(int64_t)pl * gridDim.x + blockIdx.x] = h[pl];
 }
 
+// Level A, pass 2: the same particles, scattered plane by plane into tmp as
+// (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1).
 template <int ASSIGN>
-__global__ __launch_bounds__(256) void scatter_kernel(pk_catalog gal, pk_catalog ran, SortGeom g,
-                                                      uint32_t* cursor, const double* scal, float4* sorted) {
-  const int64_t ntot = gal.n + ran.n;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__global__ __launch_bounds__(256) void plane_scatter_kernel(pk_catalog gal, pk_catalog ran, SortGeom g, int64_t per,
+                                                            const uint32_t* phoff, const double* scal, float4* tmp) {
+  extern __shared__ uint32_t cur[];
+  for (int pl = threadIdx.x; pl < g.N; pl += blockDim.x) cur[pl] = phoff[(int64_t)pl * gridDim.x + blockIdx.x];
+  __syncthreads();
   const float alpha = (float)scal[kAlpha];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += stride) {
+  const int64_t ntot = gal.n + ran.n;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < ntot ? i0 + per : ntot;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const bool isg = i < gal.n;
     const float* q = isg ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
     const float x = q[0], y = q[1], z = q[2];
     if (!valid_particle<false>(g, x, y, z, nullptr)) continue;  // flags were raised by the histogram
-    const int iy = base_index<ASSIGN>(grid_coord(y, g.bmin[1], g.invH), g.N);
     const int iz = base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N);
-    const uint32_t slot = atomicAdd(&cursor[(int64_t)iz * g.N + iy], 1u);
+    const uint32_t slot = atomicAdd(&cur[iz], 1u);
     const float w = isg ? gal.w[i] : -alpha * ran.w[i - gal.n];
-    if (slot < (uint32_t)ntot) sorted[slot] = make_float4(x, y, z, w);
+    if (slot < (uint32_t)ntot) tmp[slot] = make_float4(x, y, z, w);
+  }
+}
+
+// Exclusive scan of a[0, n) (n <= 2 * NT) held in LDS, by a block of NT threads; writes
+// the starts back into a and returns the total to every thread.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan_lds(uint32_t* a, int n) {
+  __shared__ uint32_t wsum[NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t v0 = 2 * tid < n ? a[2 * tid] : 0u;
+  const uint32_t v1 = 2 * tid + 1 < n ? a[2 * tid + 1] : 0u;
+  const uint32_t loc = v0 + v1;
+  uint32_t inc = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t ex = inc - loc, tot = 0;
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wv) ex += wsum[w];
+    tot += wsum[w];
+  }
+  if (2 * tid < n) a[2 * tid] = ex;
+  if (2 * tid + 1 < n) a[2 * tid + 1] = ex + v0;
+  __syncthreads();
+  return tot;
+}
+
+// Level B: one block per z plane sorts the plane's particles by row y and writes the
+// global row offsets rowoff[z * N + y] (rowoff[N * N] = total).
+template <int ASSIGN>
+__global__ __launch_bounds__(1024) void row_sort_kernel(const float4* __restrict__ tmp, const uint32_t* __restrict__ phoff,
+                                                        int B, SortGeom g, float4* __restrict__ sorted,
+                                                        uint32_t* __restrict__ rowoff) {
+  extern __shared__ uint32_t hc[];  // N counts -> starts; N cursors
+  uint32_t* cur = hc + g.N;
+  const int pl = blockIdx.x;
+  const uint32_t lo = phoff[(int64_t)pl * B], hi = phoff[(int64_t)(pl + 1) * B];
+  for (int i = threadIdx.x; i < g.N; i += blockDim.x) hc[i] = 0u;
+  __syncthreads();
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+    atomicAdd(&hc[base_index<ASSIGN>(grid_coord(tmp[i].y, g.bmin[1], g.invH), g.N)], 1u);
+  __syncthreads();
+  block_scan_lds<1024>(hc, g.N);
+  for (int i = threadIdx.x; i < g.N; i += blockDim.x) {
+    cur[i] = hc[i];
+    rowoff[(int64_t)pl * g.N + i] = lo + hc[i];
+  }
+  if (pl == g.N - 1 && threadIdx.x == 0) rowoff[(int64_t)g.N * g.N] = hi;
+  __syncthreads();
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const float4 q = tmp[i];
+    const uint32_t pos = atomicAdd(&cur[base_index<ASSIGN>(grid_coord(q.y, g.bmin[1], g.invH), g.N)], 1u);
+    if (lo + pos < hi) sorted[lo + pos] = q;
   }
 }
 
@@ -250,9 +314,9 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* blocksum, int 
   if (t < nb) blocksum[t] = a[t] - v;
 }
 
-// Row offsets and the per-row write cursors (the counters are overwritten in place).
-__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* cnt_cursor, int64_t n, const uint32_t* blocksum,
-                                                        uint32_t* rowoff) {
+// Exclusive scan, second level: out[i] = offset of element i (in place allowed), out[n] = total.
+__global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t* cnt, int64_t n, const uint32_t* blocksum,
+                                                        uint32_t* out) {
   constexpr int PER = kScanChunk / 256;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * PER;
   uint32_t v[PER];
@@ -260,7 +324,7 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* cnt_cursor, in
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int64_t i = base + k;
-    v[k] = i < n ? cnt_cursor[i] : 0u;
+    v[k] = i < n ? cnt[i] : 0u;
     s += v[k];
   }
   __shared__ uint32_t a[256];
@@ -276,13 +340,10 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* cnt_cursor, in
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int64_t i = base + k;
-    if (i < n) {
-      rowoff[i] = run;
-      cnt_cursor[i] = run;
-    }
+    if (i < n) out[i] = run;
     run += v[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) rowoff[n] = run;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[n] = run;
 }
 
 static SortGeom sort_geom(const Plan& p) {
@@ -299,29 +360,43 @@ static SortGeom sort_geom(const Plan& p) {
   return g;
 }
 
+int sort_blocks(int64_t ntot) {
+  int64_t b = (ntot + 255) / 256;
+  if (b > kSortBlocks) b = kSortBlocks;
+  return b < 1 ? 1 : (int)b;
+}
+
 hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s) {
   const SortGeom g = sort_geom(p);
   const int64_t ntot = p.n_gal + p.n_ran;
-  int blocks = (int)((ntot + 255) / 256);
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  uint32_t* rowcnt = at<uint32_t>(ws, p.off_rowcnt);
+  const int B = sort_blocks(ntot);
+  const int64_t per = (ntot + B - 1) / B;
+  uint32_t* ph = at<uint32_t>(ws, p.off_rowcnt);
+  const size_t shA = sizeof(uint32_t) * p.N;
   if (p.assign == PK_CIC)
-    hipLaunchKernelGGL(hist_kernel<PK_CIC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt, at<int>(ws, p.off_flags));
+    hipLaunchKernelGGL(plane_hist_kernel<PK_CIC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph, at<int>(ws, p.off_flags));
   else
-    hipLaunchKernelGGL(hist_kernel<PK_TSC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt, at<int>(ws, p.off_flags));
-  const int64_t nrow = (int64_t)p.N * p.N;
-  const int nb = (int)((nrow + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(plane_hist_kernel<PK_TSC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph, at<int>(ws, p.off_flags));
+  const int64_t nph = (int64_t)p.N * B;
+  const int nb = (int)((nph + kScanChunk - 1) / kScanChunk);
   uint32_t* bsum = at<uint32_t>(ws, p.off_blocksum);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, rowcnt, nrow, bsum);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, ph, nph, bsum);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
-  hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(256), 0, s, rowcnt, nrow, bsum, at<uint32_t>(ws, p.off_rowoff));
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(256), 0, s, ph, nph, bsum, ph);
+  float4* tmp = at<float4>(ws, p.off_tmp);
   if (p.assign == PK_CIC)
-    hipLaunchKernelGGL(scatter_kernel<PK_CIC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt,
-                       at<double>(ws, p.off_scalars), at<float4>(ws, p.off_sorted));
+    hipLaunchKernelGGL(plane_scatter_kernel<PK_CIC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph,
+                       at<const double>(ws, p.off_scalars), tmp);
   else
-    hipLaunchKernelGGL(scatter_kernel<PK_TSC>, dim3(blocks), dim3(256), 0, s, gal, ran, g, rowcnt,
-                       at<double>(ws, p.off_scalars), at<float4>(ws, p.off_sorted));
+    hipLaunchKernelGGL(plane_scatter_kernel<PK_TSC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph,
+                       at<const double>(ws, p.off_scalars), tmp);
+  const size_t shB = sizeof(uint32_t) * 2 * p.N;
+  if (p.assign == PK_CIC)
+    hipLaunchKernelGGL(row_sort_kernel<PK_CIC>, dim3(p.N), dim3(1024), shB, s, tmp, ph, B, g,
+                       at<float4>(ws, p.off_sorted), at<uint32_t>(ws, p.off_rowoff));
+  else
+    hipLaunchKernelGGL(row_sort_kernel<PK_TSC>, dim3(p.N), dim3(1024), shB, s, tmp, ph, B, g,
+                       at<float4>(ws, p.off_sorted), at<uint32_t>(ws, p.off_rowoff));
   return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ class PkResult(ctypes.Structure):
 
 EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_result_doubles",
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
-           "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name"]
+           "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
+           "pk_workspace_size_batch", "pk_multipoles_batch"]
 
 _lib = None
 
@@ -72,6 +73,9 @@ def load():
     lib.pk_status_string.restype = c_char_p
     lib.pk_last_error.argtypes = [ctypes.c_char_p, c_size_t]
     lib.pk_last_error.restype = c_size_t
+    lib.pk_workspace_size_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, P(c_size_t)]
+    lib.pk_multipoles_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, c_void_p, c_size_t,
+                                        P(PkResult), P(c_int32), c_void_p]
     lib.pk_set_stage_timing.argtypes = [c_int32]
     lib.pk_stage_times.argtypes = [POINTER(c_double), c_int32]
     lib.pk_stage_times.restype = c_int32

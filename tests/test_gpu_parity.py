@@ -212,3 +212,39 @@ def test_error_zero_random_weight(pk):
     def f(c):
         c.w[:] = 0.0
     _errcase(pk, mutate_ran=f, expect=-3)
+
+
+# ------------------------------------------------------------------------- batches
+
+def test_batch_matches_single_calls_and_oracle(pk):
+    """Uneven mocks of two size classes over two lanes; every mock equals its own single
+    call and the oracle; a mock with an out-of-box particle reports PK_ERANGE alone."""
+    mocks = []
+    for i in range(7):
+        N = 32 if i % 3 else 64
+        L = 400.0 + 50 * i
+        box_min = (-L / 2, -L / 2, 500.0)
+        ng = 1500 + 700 * i
+        gal = catalogs.uniform_box(ng, box_min, L, 100 + i, ng / L ** 3)
+        ran = catalogs.uniform_box(10 * ng, box_min, L, 200 + i, ng / L ** 3)
+        if i == 4:
+            gal.pos[3, 2] = 499.0          # outside the box
+        cfg = catalogs.config_dict(N, box_min, L, assign=2 if i % 2 else 3, dn=1)
+        mocks.append((gal, ran, cfg))
+    dg = [pk.DeviceCatalog.from_host(m[0]) for m in mocks]
+    dr = [pk.DeviceCatalog.from_host(m[1]) for m in mocks]
+    res, st = pk.pk_multipoles_batch(dg, dr, [m[2] for m in mocks], lanes=2)
+    assert st[4] == -2 and res[4] is None
+    for i, (gal, ran, cfg) in enumerate(mocks):
+        if i == 4:
+            continue
+        assert st[i] == 0
+        single = pk.pk_multipoles(dg[i], dr[i], cfg)
+        np.testing.assert_array_equal(res[i]["nmodes"], single["nmodes"])
+        raw = np.abs(single["P0"]) + single["noise"]
+        ok = single["nmodes"] > 0
+        for ell in (0, 2, 4):
+            assert np.max(np.abs(res[i]["P%d" % ell][ok] - single["P%d" % ell][ok]) / raw[ok]) < 1e-6
+        if i in (0, 5):
+            ref = est.pk_multipoles(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
+            compare(res[i], ref, cfg)
