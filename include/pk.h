@@ -172,6 +172,45 @@ pk_status pk_set_stage_timing(int32_t enable);
 int32_t pk_stage_times(double* ms, int32_t n);
 const char* pk_stage_name(int32_t i);
 
+/* ---------------------------------------------------------------------------------
+ * Coarse-grid correction network. Callers: the correction that maps multipoles measured
+ * on a coarse grid to the fine-grid estimate (aliasing and window), trained on pairs of
+ * coarse- and fine-grid measurements made by pk_multipoles itself; the plain fine-grid
+ * estimator stays the reference and the fallback.
+ * Shape: din inputs (1..64), 3 hidden layers of width 128 with SiLU, dout outputs (1..16).
+ * Canonical parameter vector (float32, device): for each of the 4 layers, W [in][out]
+ * row-major then b [out]; pk_mlp_num_params() floats. The state buffer (device,
+ * pk_mlp_state_bytes) holds FP32 master weights, Adam moments and BF16 copies; the
+ * workspace (device, pk_mlp_workspace_bytes(rows)) holds activations for `rows` rows.
+ * GEMMs run on BF16 MFMA with FP32 accumulation; reductions have a fixed order. All
+ * calls queue work on hip_stream and return; results are valid after the stream syncs.
+ * --------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t din;
+  int32_t dout;
+  int32_t width;  /* must be 128 */
+  int32_t depth;  /* must be 3 */
+} pk_mlp_shape;
+
+size_t pk_mlp_state_bytes(const pk_mlp_shape* shape);
+size_t pk_mlp_workspace_bytes(const pk_mlp_shape* shape, int64_t rows);
+int64_t pk_mlp_num_params(const pk_mlp_shape* shape);
+/* Loads parameters (device float32, canonical order), zeroes the Adam moments. */
+pk_status pk_mlp_set_params(const pk_mlp_shape* shape, void* state, const float* d_params, void* hip_stream);
+pk_status pk_mlp_get_params(const pk_mlp_shape* shape, const void* state, float* d_params, void* hip_stream);
+/* y[rows][dout] = network(x[rows][din]), float32 device arrays. */
+pk_status pk_mlp_forward(const pk_mlp_shape* shape, const void* state, const float* d_x, int64_t rows, float* d_y,
+                         void* workspace, size_t workspace_bytes, void* hip_stream);
+/* Mean-squared-error loss against t[rows][dout] (to *d_loss, float32 device scalar) and
+ * its gradient (canonical order, to d_grads unless NULL); parameters unchanged. */
+pk_status pk_mlp_gradients(const pk_mlp_shape* shape, const void* state, const float* d_x, const float* d_t,
+                           int64_t rows, float* d_grads, float* d_loss, void* workspace, size_t workspace_bytes,
+                           void* hip_stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8; `step` counts from 1) on the batch. */
+pk_status pk_mlp_train_step(const pk_mlp_shape* shape, void* state, const float* d_x, const float* d_t, int64_t rows,
+                            float lr, int32_t step, float* d_loss, void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+
 /* Number of LOS-weighted grids for ell_max (1, 7, 22), and the exponents of grid m. */
 int32_t pk_num_grids(int32_t ell_max);
 pk_status pk_monomial(int32_t m, int32_t* a, int32_t* b, int32_t* c);

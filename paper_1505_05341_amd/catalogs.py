@@ -185,3 +185,100 @@ def small_clustered(N=64, seed=7, L=600.0, nbar=1.0e-3, ran_factor=10.0, N_field
     kw = dict(assign=2, ell_max=4, dn=1)
     kw.update(cfg_kw)
     return gal, ran, config_dict(N, box_min, L, **kw)
+
+
+# ---------------------------------------------------------------------------------
+# Device generator (same recipe as lognormal_rsd, run with torch on the GPU). Input
+# synthesis only: the estimator never calls it. Deterministic for a given seed on a
+# given GPU model (torch's counter-based device generator).
+# ---------------------------------------------------------------------------------
+
+def lognormal_rsd_device(*, N_field, L, center, nbar, seed, amp=2.0e4, k0=0.1, slope=-1.5, f=0.75, b=2.0,
+                         ran_factor=20.0, P_fkp=1.0e4, observer=(0.0, 0.0, 0.0), device="cuda"):
+    """Lognormal RSD mock made on the GPU; returns (gal, ran, box_min) with gal and ran
+    DeviceCatalog objects (float32 tensors on `device`)."""
+    import torch
+    from .api import DeviceCatalog
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    N = int(N_field)
+    H = L / N
+    f64 = torch.float64
+    box_min = torch.tensor([c - 0.5 * L for c in center], dtype=f64, device=device)
+    kx = 2.0 * np.pi * torch.fft.fftfreq(N, d=H, dtype=f64, device=device)
+    kz = 2.0 * np.pi * torch.fft.rfftfreq(N, d=H, dtype=f64, device=device)
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    kmag = torch.sqrt(k2)
+    Pk = torch.where(kmag > 0, amp * (kmag.clamp_min(1e-30) / k0) ** slope, torch.zeros_like(kmag))
+    xi = torch.fft.irfftn(Pk, s=(N, N, N)) * (N ** 3 / L ** 3)
+    del Pk
+    xig = torch.log1p(xi)
+    del xi
+    sigma2 = float(xig[0, 0, 0])
+    PG = torch.fft.rfftn(xig).real * (L ** 3 / N ** 3)
+    del xig
+    PG.clamp_(min=0.0)
+    PG[0, 0, 0] = 0.0
+    white = torch.randn((N, N, N), generator=gen, dtype=f64, device=device)
+    Gk = torch.fft.rfftn(white)
+    del white
+    Gk *= torch.sqrt(PG / H ** 3)
+    del PG
+    G = torch.fft.irfftn(Gk, s=(N, N, N))
+    lam = nbar * H ** 3 * torch.exp(G - 0.5 * sigma2)
+    del G
+    counts = torch.poisson(lam.reshape(-1), generator=gen).to(torch.int64)
+    del lam
+    cells = torch.repeat_interleave(torch.arange(N ** 3, device=device), counts)
+    del counts
+    ng = int(cells.numel())
+    ijk = torch.stack([cells // (N * N), (cells // N) % N, cells % N], dim=1)
+    x = box_min[None, :] + (ijk.to(f64) + torch.rand((ng, 3), generator=gen, dtype=f64, device=device)) * H
+    fac = torch.where(k2 > 0, 1.0 / (b * k2.clamp_min(1e-30)), torch.zeros_like(k2))
+    kvec = (kx[:, None, None], kx[None, :, None], kz[None, None, :])
+    disp = torch.empty((ng, 3), dtype=f64, device=device)
+    for ax in range(3):
+        psi = torch.fft.irfftn(1j * kvec[ax] * fac * Gk, s=(N, N, N))
+        disp[:, ax] = psi[ijk[:, 0], ijk[:, 1], ijk[:, 2]]
+        del psi
+    del Gk, fac, k2, kmag, ijk, cells
+    obs = torch.tensor(observer, dtype=f64, device=device)
+    d = x - obs[None, :]
+    rhat = d / torch.linalg.norm(d, dim=1, keepdim=True)
+    s = x + f * torch.sum(disp * rhat, dim=1, keepdim=True) * rhat
+    del d, rhat, disp, x
+    s = box_min[None, :] + torch.remainder(s - box_min[None, :], L)
+    w = float(np.float32(1.0 / (1.0 + nbar * P_fkp)))
+    gpos = _inside_device(s, box_min, L)
+    nr = int(round(ran_factor * ng))
+    rpos = _inside_device(box_min[None, :] + torch.rand((nr, 3), generator=gen, dtype=f64, device=device) * L,
+                          box_min, L)
+    gal = DeviceCatalog(gpos, torch.full((ng,), w, dtype=torch.float32, device=device),
+                        torch.full((ng,), nbar, dtype=torch.float32, device=device))
+    ran = DeviceCatalog(rpos, torch.full((nr,), w, dtype=torch.float32, device=device),
+                        torch.full((nr,), nbar, dtype=torch.float32, device=device))
+    return gal, ran, tuple(float(v) for v in box_min.cpu().numpy())
+
+
+def _inside_device(pos64, box_min, L):
+    """float32 positions kept in [box_min, box_min + L) when compared in float64."""
+    import torch
+    p = pos64.to(torch.float32)
+    lo = box_min[None, :]
+    hi = lo + L
+    for _ in range(4):
+        over = p.to(torch.float64) >= hi
+        if not bool(over.any()):
+            break
+        p = torch.where(over, torch.nextafter(p, torch.full_like(p, -np.inf)), p)
+    for _ in range(4):
+        under = p.to(torch.float64) < lo
+        if not bool(under.any()):
+            break
+        p = torch.where(under, torch.nextafter(p, torch.full_like(p, np.inf)), p)
+    return p.contiguous()
+
+
+def device_catalog_to_host(cat):
+    return Catalog(cat.pos.cpu().numpy(), cat.w.cpu().numpy(), cat.nbar.cpu().numpy())

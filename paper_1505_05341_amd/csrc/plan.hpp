@@ -13,7 +13,7 @@ constexpr int kMaxGrids = 22;
 constexpr int kMaxGroups = 9;
 constexpr int kMaxMembers = 5;
 constexpr int kMaxTiles = 64;       // kx tiles of 16 columns up to N = 2048
-constexpr int kStatsBlocks = 512;   // blocks of the catalogue-scalar reduction
+constexpr int kStatsBlocks = 2048;  // blocks of the catalogue-scalar reduction
 constexpr int kScanChunk = 4096;    // counters per scan block
 constexpr int kSortBlocks = 2048;   // level-A sort blocks (one contiguous particle range each)
 constexpr int kNumSums = 6;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise

