@@ -50,7 +50,7 @@ __device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&
 }
 
 constexpr int XTHREADS = 512;
-constexpr int XCHUNK = 2048;   // particles per LDS chunk
+constexpr int XCHUNK = 1024;   // particles per LDS chunk
 constexpr int XPER = XCHUNK / XTHREADS;  // particles per thread per chunk
 
 // Bytes of the gather-phase LDS area: pa float4[XCHUNK] (fx, w' W_y W_z, rx, ry),
@@ -236,7 +236,13 @@ __global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))
   static_assert(NP * F::T <= XTHREADS, "row pairs do not fit the block");
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
-  const int y = blockIdx.x, z = blockIdx.y, part = blockIdx.z;
+  // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
+  // the rows of planes [j N/8, (j+1) N/8) in order and the source rows that neighbouring
+  // target rows share stay in that XCD's L2.
+  const int part = blockIdx.z;
+  const uint32_t lin = blockIdx.x + blockIdx.y * (uint32_t)N;
+  const uint32_t logical = (lin & 7u) * (uint32_t)(N * N / 8) + (lin >> 3);
+  const int y = (int)(logical % N), z = (int)(logical / N);
   const int g0 = part * GB;
   const int ng = G - g0 < GB ? G - g0 : GB;
 
