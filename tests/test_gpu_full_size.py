@@ -1,0 +1,142 @@
+"""Parity at the full size of the benchmark workload (clustered RSD mock, 9.9e7
+particles, CIC on 512^3, ell = 0, 2, 4, 128 bins of 2 k_f), in the launch configuration
+bench.py times. The oracle cannot redo the whole 22-grid estimator at this size in a
+test, so two checks it can afford are made instead:
+
+* sampled outputs: rows of the x-transformed LOS-weighted grids (the fused assignment
+  and x FFT, Sec. 3 Eqs. 11, 13), row by row against the FP64 oracle;
+* a property that holds at any size: with the line of sight fixed to z every monomial
+  grid is r_z^n times the density grid, so the whole estimator (all three passes, the
+  contraction of Eqs. 10 and 12 and the binning) must equal the single-FFT
+  plane-parallel form (2l+1) <|A0|^2 L_l(k_z/k)> / I (minus the noise for l = 0),
+  which the oracle computes with one FFT; compared bin by bin with the same bar as the
+  small parity tests.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import direct
+from oracle import estimator as est
+from paper_1505_05341_amd import catalogs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+TOL = 1e-5
+# Rows: the weights of galaxies and randoms cancel in a row (the row is a density
+# contrast), so the error is measured against the sum of |terms| (l1) instead of the
+# row's own size. The kernel takes u = (x - box_min) N / L in FP32 with box_min and N / L
+# rounded to FP32, so every particle's offset inside its cell, hence every CIC weight,
+# is off by up to ~|u| 2^-24, and near the top of the box (u ~ 512) that error has the
+# same sign for all particles of a row: up to 512 x 6e-8 = 3e-5 of l1 in the worst case
+# (observed 1e-7 to 1.5e-5), on top of a few eps_32 from the cell sums and the radix
+# stages. A lost or misplaced particle would show as ~1 / 1500 ~ 7e-4 of l1.
+XTOL = 4e-5
+
+
+@pytest.fixture(scope="module")
+def workload():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1505_05341_amd as pk
+    pk.load()
+    t = time.time()
+    gal, ran, cfg = catalogs.clustered_rsd_512()
+    print("full-size workload: %d galaxies + %d randoms, N = %d (%.1f s)" % (gal.n, ran.n, cfg["N"], time.time() - t),
+          flush=True)
+    return pk, gal, ran, cfg
+
+
+def test_sampled_x_rows_full_size(workload):
+    pk, gal, ran, cfg = workload
+    from paper_1505_05341_amd import native
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    ws, layout = pk.stage_xgrids(g, r, cfg)
+    c = est.Config(**cfg)
+    N = c.N
+    alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    wp = est.signed_weights(gal.w, ran.w, alpha)
+    rng = np.random.default_rng(11)
+    rows = [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(4)] + [(0, 0), (N - 1, N - 1)]
+    # particles whose CIC stencil can reach a sampled row (a superset: the oracle row
+    # function itself keeps only those that reach it)
+    u = est.grid_units(pos, c.box_min, c.L, N)
+    jy = np.floor(u[:, 1]).astype(np.int64) % N
+    jz = np.floor(u[:, 2]).astype(np.int64) % N
+    for iy, iz in rows:
+        near = (((iy - jy) % N) <= 1) & (((iz - jz) % N) <= 1)
+        sub_pos, sub_w = pos[near], wp[near]
+        # sum over the row of |w'| W_x W_y W_z: bounds the sum of |terms| of every grid
+        l1 = est.x_transformed_row(sub_pos, np.abs(sub_w), c, (0, 0, 0), iy, iz)[0].real
+        for m in (0, 4, 17):
+            X = pk.xgrid_view(ws, layout, m, N)
+            kx = layout[m][1]
+            got = X[iz, iy].cpu().numpy()
+            got = got[:, 0] + 1j * got[:, 1]
+            ref = est.x_transformed_row(sub_pos, sub_w, c, native.monomial(m), iy, iz)[:kx]
+            err = np.max(np.abs(got - ref)) / l1
+            print("row", (iy, iz), "grid", m, "particles", int(near.sum()), "err %.2e" % err, flush=True)
+            assert err < XTOL, (iy, iz, m, err)
+    del ws
+
+
+def test_plane_parallel_full_size(workload):
+    pk, gal, ran, cfg = workload
+    cfg = dict(cfg, los=1)
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    got = pk.pk_multipoles(g, r, cfg)
+    c = est.Config(**cfg)
+    N, nb = c.N, c.nbins
+    t = time.time()
+    alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
+    assert abs(got["alpha"] - alpha) <= 1e-12 * abs(alpha)
+    assert abs(got["I"] - I) <= 1e-12 * abs(I)
+    assert abs(got["S"] - S) <= 1e-12 * abs(S)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    wp = est.signed_weights(gal.w, ran.w, alpha)
+    A0 = np.fft.fftn(est.assign_to_grid(pos, wp, c))
+    del pos, wp
+    print("oracle density grid and FFT: %.1f s" % (time.time() - t), flush=True)
+    # the plane-parallel form, summed over the full lattice one kx plane at a time
+    nv = est.mode_lattice(N)
+    Wi, Ci = est.window_and_alias(N, c.assign)
+    ny = nv[:, None]
+    nz = nv[None, :]
+    wyz = Wi[:, None] ** 2 * Wi[None, :] ** 2
+    cyz = Ci[:, None] * Ci[None, :]
+    K2 = (nb * c.dn) ** 2
+    cnt = np.zeros(nb)
+    ksum = np.zeros(nb)
+    nsum = np.zeros(nb)
+    qsum = {ell: np.zeros(nb) for ell in (0, 2, 4)}
+    for ix in range(N):
+        q2 = int(nv[ix]) ** 2 + ny * ny + nz * nz
+        sel = (q2 > 0) & (q2 < K2)
+        b = est.isqrt_array(q2[sel]) // c.dn
+        W2 = (Wi[ix] ** 2 * wyz)[sel]
+        mu = np.broadcast_to(nz, q2.shape)[sel] / np.sqrt(q2[sel])
+        q = np.abs(A0[ix][sel]) ** 2 / W2
+        cnt += np.bincount(b, minlength=nb)
+        ksum += np.bincount(b, weights=np.sqrt(q2[sel]), minlength=nb)
+        nsum += np.bincount(b, weights=S * Ci[ix] * cyz[sel] / W2, minlength=nb)
+        for ell in (0, 2, 4):
+            qsum[ell] += np.bincount(b, weights=(2 * ell + 1) * q * direct.legendre(ell, mu), minlength=nb)
+    del A0
+    print("oracle total: %.1f s" % (time.time() - t), flush=True)
+    np.testing.assert_array_equal(got["nmodes"], cnt.astype(np.int64))
+    ok = cnt > 0
+    den = I * np.maximum(cnt, 1)
+    noise = nsum / den
+    np.testing.assert_allclose(got["noise"][ok], noise[ok], rtol=1e-5)
+    kf = 2 * np.pi / c.L
+    np.testing.assert_allclose(got["k_eff"][ok], kf * ksum[ok] / cnt[ok], rtol=1e-6)
+    ref = {ell: qsum[ell] / den - (noise if ell == 0 else 0.0) for ell in (0, 2, 4)}
+    raw = np.abs(ref[0]) + noise
+    for ell in (0, 2, 4):
+        e = np.max(np.abs(got["P%d" % ell][ok] - ref[ell][ok]) / raw[ok])
+        print("ell", ell, "e_l %.2e" % e, flush=True)
+        assert e <= TOL, (ell, e)
