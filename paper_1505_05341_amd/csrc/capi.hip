@@ -131,8 +131,10 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_tables = take(sizeof(GroupTable) + sizeof(TileTable));
   p.off_rowcnt = take(sizeof(uint32_t) * ((size_t)p.N * sort_blocks(n_gal + n_ran) + 1));  // plane histograms
   p.off_rowoff = take(sizeof(uint32_t) * (nrow + 1));
+  p.off_rowhist = take(sizeof(uint32_t) * ((size_t)nrow * kRowHistParts + 1));  // per-part row counts
   p.off_blocksum = take(sizeof(uint32_t) * 1024);
   p.off_tmp = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
+  p.off_rowkey = take(sizeof(uint16_t) * (size_t)(n_gal + n_ran));
   p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_X = take(sizeof(float) * 2 * (size_t)p.G * nrow * p.Kx);
   p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);

@@ -18,13 +18,11 @@ __device__ __forceinline__ float grid_coord(float x, float bmin, float invH) {
   return __fmul_rn(__fsub_rn(x, bmin), invH);
 }
 
+// N is a power of two (the supported grid sizes), so the periodic wrap is a mask.
 template <int ASSIGN>
 __device__ __forceinline__ int base_index(float u, int N) {
   const float t = ASSIGN == PK_CIC ? u : __fadd_rn(u, 0.5f);
-  int i = (int)floorf(t);
-  i %= N;
-  if (i < 0) i += N;
-  return i;
+  return (int)floorf(t) & (N - 1);
 }
 
 // Offset of u from its base node (f for CIC, d for TSC).

@@ -16,6 +16,7 @@ constexpr int kMaxTiles = 64;       // kx tiles of 16 columns up to N = 2048
 constexpr int kStatsBlocks = 2048;  // blocks of the catalogue-scalar reduction
 constexpr int kScanChunk = 4096;    // counters per scan block
 constexpr int kSortBlocks = 2048;   // level-A sort blocks (one contiguous particle range each)
+constexpr int kRowHistParts = 4;    // level-B blocks per plane
 constexpr int kNumSums = 6;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise
 
 // Device scalars written by the catalogue-scalar kernels.
@@ -87,7 +88,7 @@ struct Plan {
   TileTable tiles;
   // workspace offsets (bytes)
   size_t off_scalars, off_partials, off_flags, off_tw, off_invw2, off_alias, off_tables;
-  size_t off_rowcnt, off_rowoff, off_blocksum, off_tmp, off_sorted, off_X, off_H, off_zpart, off_result;
+  size_t off_rowcnt, off_rowoff, off_rowhist, off_blocksum, off_tmp, off_rowkey, off_sorted, off_X, off_H, off_zpart, off_result;
   size_t total;
   size_t H_group_stride;   // float2 elements per group in H
   int64_t result_doubles;

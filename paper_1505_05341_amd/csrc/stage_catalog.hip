@@ -215,39 +215,21 @@ __global__ __launch_bounds__(256) void plane_hist_kernel(pk_catalog gal, pk_cata
   for (int pl = threadIdx.x; pl < g.N; pl += blockDim.x) ph[(int64_t)pl * gridDim.x + blockIdx.x] = h[pl];
 }
 
-// Level A, pass 2: the same particles, scattered plane by plane into tmp as
-// (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1).
-template <int ASSIGN>
-__global__ __launch_bounds__(256) void plane_scatter_kernel(pk_catalog gal, pk_catalog ran, SortGeom g, int64_t per,
-                                                            const uint32_t* phoff, const double* scal, float4* tmp) {
-  extern __shared__ uint32_t cur[];
-  for (int pl = threadIdx.x; pl < g.N; pl += blockDim.x) cur[pl] = phoff[(int64_t)pl * gridDim.x + blockIdx.x];
-  __syncthreads();
-  const float alpha = (float)scal[kAlpha];
-  const int64_t ntot = gal.n + ran.n;
-  const int64_t i0 = (int64_t)blockIdx.x * per;
-  const int64_t i1 = i0 + per < ntot ? i0 + per : ntot;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const bool isg = i < gal.n;
-    const float* q = isg ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
-    const float x = q[0], y = q[1], z = q[2];
-    if (!valid_particle<false>(g, x, y, z, nullptr)) continue;  // flags were raised by the histogram
-    const int iz = base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N);
-    const uint32_t slot = atomicAdd(&cur[iz], 1u);
-    const float w = isg ? gal.w[i] : -alpha * ran.w[i - gal.n];
-    if (slot < (uint32_t)ntot) tmp[slot] = make_float4(x, y, z, w);
-  }
-}
-
-// Exclusive scan of a[0, n) (n <= 2 * NT) held in LDS, by a block of NT threads; writes
+// Exclusive scan of a[0, n) (n <= 4 NT) held in LDS, by a block of NT threads; writes
 // the starts back into a and returns the total to every thread.
 template <int NT>
 __device__ __forceinline__ uint32_t block_scan_lds(uint32_t* a, int n) {
+  constexpr int PER = 4;
   __shared__ uint32_t wsum[NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t v0 = 2 * tid < n ? a[2 * tid] : 0u;
-  const uint32_t v1 = 2 * tid + 1 < n ? a[2 * tid + 1] : 0u;
-  const uint32_t loc = v0 + v1;
+  uint32_t v[PER];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = tid * PER + j;
+    v[j] = idx < n ? a[idx] : 0u;
+    loc += v[j];
+  }
   uint32_t inc = loc;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -261,38 +243,227 @@ __device__ __forceinline__ uint32_t block_scan_lds(uint32_t* a, int n) {
     if (w < wv) ex += wsum[w];
     tot += wsum[w];
   }
-  if (2 * tid < n) a[2 * tid] = ex;
-  if (2 * tid + 1 < n) a[2 * tid + 1] = ex + v0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = tid * PER + j;
+    if (idx < n) a[idx] = ex;
+    ex += v[j];
+  }
   __syncthreads();
   return tot;
 }
 
-// Level B: one block per z plane sorts the plane's particles by row y and writes the
-// global row offsets rowoff[z * N + y] (rowoff[N * N] = total).
+// Both scatters write through an LDS tile: a tile of particles is counting-sorted by
+// bucket in LDS and then copied out bucket run by bucket run, so that consecutive
+// threads store consecutive slots of one bucket (runs of ~tile/buckets particles)
+// instead of scattering 16-byte stores over all buckets, which costs a partial-line
+// write per particle.
+constexpr int kSortThreads = 512;
+constexpr int kSortTile = 2048;
+constexpr int kSortPer = kSortTile / kSortThreads;
+
+// LDS of one staged scatter: cur, tcnt, gb (uint32[nb] each), stage float4[tile],
+// skey and sval (uint16[tile] each).
+__host__ __device__ constexpr size_t staged_lds_bytes(int nb) {
+  return (size_t)3 * nb * 4 + (size_t)kSortTile * (16 + 2 + 2);
+}
+
+// Level A, pass 2: the same particles, scattered plane by plane into tmp as
+// (x, y, z, w') with w' = w for galaxies and -alpha w for randoms (Eq. 1); the row index
+// of each particle goes to rowkey at the same slot, for level B.
 template <int ASSIGN>
-__global__ __launch_bounds__(1024) void row_sort_kernel(const float4* __restrict__ tmp, const uint32_t* __restrict__ phoff,
-                                                        int B, SortGeom g, float4* __restrict__ sorted,
-                                                        uint32_t* __restrict__ rowoff) {
-  extern __shared__ uint32_t hc[];  // N counts -> starts; N cursors
-  uint32_t* cur = hc + g.N;
-  const int pl = blockIdx.x;
-  const uint32_t lo = phoff[(int64_t)pl * B], hi = phoff[(int64_t)(pl + 1) * B];
-  for (int i = threadIdx.x; i < g.N; i += blockDim.x) hc[i] = 0u;
-  __syncthreads();
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    atomicAdd(&hc[base_index<ASSIGN>(grid_coord(tmp[i].y, g.bmin[1], g.invH), g.N)], 1u);
-  __syncthreads();
-  block_scan_lds<1024>(hc, g.N);
-  for (int i = threadIdx.x; i < g.N; i += blockDim.x) {
-    cur[i] = hc[i];
-    rowoff[(int64_t)pl * g.N + i] = lo + hc[i];
+__global__ __launch_bounds__(kSortThreads) void plane_scatter_kernel(pk_catalog gal, pk_catalog ran, SortGeom g,
+                                                                     int64_t per, const uint32_t* phoff,
+                                                                     const double* scal, float4* tmp,
+                                                                     uint16_t* rowkey) {
+  extern __shared__ __align__(16) uint32_t sm[];
+  const int nb = g.N;
+  uint32_t* cur = sm;        // next global slot of each plane for this block
+  uint32_t* tcnt = cur + nb;  // tile counts, then tile starts
+  uint32_t* gb = tcnt + nb;   // global slot of the first particle of each plane's run in the tile
+  float4* stage = reinterpret_cast<float4*>(sm + 3 * nb);
+  uint16_t* skey = reinterpret_cast<uint16_t*>(stage + kSortTile);
+  uint16_t* sval = skey + kSortTile;
+  const int tid = threadIdx.x;
+  for (int pl = tid; pl < nb; pl += kSortThreads) cur[pl] = phoff[(int64_t)pl * gridDim.x + blockIdx.x];
+  const float alpha = (float)scal[kAlpha];
+  const int64_t ntot = gal.n + ran.n;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < ntot ? i0 + per : ntot;
+  // raw (x, y, z, w) of this thread's particles of the next tile, loaded one tile ahead
+  float4 nraw[kSortPer];
+  auto load_tile = [&](int64_t t0) {
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const int64_t i = t0 + tid + j * kSortThreads;
+      if (i < i1) {
+        const bool isg = i < gal.n;
+        const float* q = isg ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
+        nraw[j] = make_float4(q[0], q[1], q[2], isg ? gal.w[i] : ran.w[i - gal.n]);
+      }
+    }
+  };
+  load_tile(i0);
+  for (int64_t t0 = i0; t0 < i1; t0 += kSortTile) {
+    float4 raw[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) raw[j] = nraw[j];
+    if (t0 + kSortTile < i1) load_tile(t0 + kSortTile);
+    __syncthreads();  // the previous tile's copy-out is done (and cur is set)
+    for (int k = tid; k < nb; k += kSortThreads) tcnt[k] = 0u;
+    __syncthreads();
+    float4 v[kSortPer];
+    int key[kSortPer], row[kSortPer];
+    uint32_t rank[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      const int64_t i = t0 + tid + j * kSortThreads;
+      key[j] = -1;
+      row[j] = 0;
+      rank[j] = 0u;
+      v[j] = raw[j];
+      // flags were raised by the histogram pass; here invalid particles are skipped
+      if (i < i1 && valid_particle<false>(g, raw[j].x, raw[j].y, raw[j].z, nullptr)) {
+        key[j] = base_index<ASSIGN>(grid_coord(raw[j].z, g.bmin[2], g.invH), g.N);
+        row[j] = base_index<ASSIGN>(grid_coord(raw[j].y, g.bmin[1], g.invH), g.N);
+        if (i >= gal.n) v[j].w = -alpha * raw[j].w;
+        rank[j] = atomicAdd(&tcnt[key[j]], 1u);
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < nb; k += kSortThreads) {
+      gb[k] = cur[k];
+      cur[k] += tcnt[k];
+    }
+    const uint32_t ntile = block_scan_lds<kSortThreads>(tcnt, nb);  // barriers inside
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      if (key[j] >= 0) {
+        const uint32_t lp = tcnt[key[j]] + rank[j];
+        stage[lp] = v[j];
+        skey[lp] = (uint16_t)key[j];
+        sval[lp] = (uint16_t)row[j];
+      }
+    }
+    __syncthreads();
+    for (uint32_t lp = tid; lp < ntile; lp += kSortThreads) {
+      const int k = skey[lp];
+      const uint32_t dst = gb[k] + (lp - tcnt[k]);
+      if (dst < (uint32_t)ntot) {
+        tmp[dst] = stage[lp];
+        rowkey[dst] = sval[lp];
+      }
+    }
   }
-  if (pl == g.N - 1 && threadIdx.x == 0) rowoff[(int64_t)g.N * g.N] = hi;
+}
+
+// Level B splits each plane into kRowParts contiguous parts, one block each, so that
+// the whole chip works on it. Pass 1: each block counts its part's particles per row
+// into rh[(plane N + row) kRowParts + part]; one exclusive scan of rh (row-major, parts
+// innermost) then gives every block its first slot in every row, and rh at part 0 is
+// the row offset.
+constexpr int kRowParts = kRowHistParts;
+
+__device__ __forceinline__ void plane_part(const uint32_t* phoff, int B, int pl, int q, uint32_t& lo, uint32_t& hi) {
+  const uint32_t a = phoff[(int64_t)pl * B], b = phoff[(int64_t)(pl + 1) * B];
+  const uint32_t len = (b - a + kRowParts - 1) / kRowParts;
+  lo = a + (uint32_t)q * len < b ? a + (uint32_t)q * len : b;
+  hi = lo + len < b ? lo + len : b;
+}
+
+__global__ __launch_bounds__(kSortThreads) void row_hist_kernel(const uint16_t* __restrict__ rowkey,
+                                                                const uint32_t* __restrict__ phoff, int B, int N,
+                                                                uint32_t* __restrict__ rh) {
+  extern __shared__ uint32_t hc[];
+  const int q = blockIdx.x, pl = blockIdx.y, tid = threadIdx.x;
+  uint32_t lo, hi;
+  plane_part(phoff, B, pl, q, lo, hi);
+  for (int i = tid; i < N; i += kSortThreads) hc[i] = 0u;
   __syncthreads();
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const float4 q = tmp[i];
-    const uint32_t pos = atomicAdd(&cur[base_index<ASSIGN>(grid_coord(q.y, g.bmin[1], g.invH), g.N)], 1u);
-    if (lo + pos < hi) sorted[lo + pos] = q;
+  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&hc[rowkey[i]], 1u);
+  __syncthreads();
+  for (int y = tid; y < N; y += kSortThreads) rh[((int64_t)pl * N + y) * kRowParts + q] = hc[y];
+}
+
+__device__ __forceinline__ void load_row_tile(const float4* __restrict__ tmp, const uint16_t* __restrict__ rowkey,
+                                              uint32_t t0, uint32_t hi, int tid, float4 (&nv)[kSortPer],
+                                              int (&nk)[kSortPer]) {
+#pragma unroll
+  for (int j = 0; j < kSortPer; ++j) {
+    const uint32_t i = t0 + tid + j * kSortThreads;
+    nk[j] = -1;
+    nv[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < hi) {
+      nk[j] = rowkey[i];
+      nv[j] = tmp[i];
+    }
+  }
+}
+
+// Pass 2: each block scatters its part by row through the LDS tile; part 0 also writes
+// the row offsets rowoff[z N + y] (rowoff[N N] = total).
+__global__ __launch_bounds__(kSortThreads) void row_sort_kernel(const float4* __restrict__ tmp,
+                                                                const uint16_t* __restrict__ rowkey,
+                                                                const uint32_t* __restrict__ phoff, int B, int N,
+                                                                const uint32_t* __restrict__ rstart,
+                                                                float4* __restrict__ sorted,
+                                                                uint32_t* __restrict__ rowoff) {
+  extern __shared__ __align__(16) uint32_t sm[];
+  const int nb = N;
+  uint32_t* cur = sm;
+  uint32_t* tcnt = cur + nb;
+  uint32_t* gb = tcnt + nb;
+  float4* stage = reinterpret_cast<float4*>(sm + 3 * nb);
+  uint16_t* skey = reinterpret_cast<uint16_t*>(stage + kSortTile);
+  const int tid = threadIdx.x;
+  const int q = blockIdx.x, pl = blockIdx.y;
+  uint32_t lo, hi;
+  plane_part(phoff, B, pl, q, lo, hi);
+  for (int y = tid; y < nb; y += kSortThreads) {
+    cur[y] = rstart[((int64_t)pl * nb + y) * kRowParts + q];
+    if (q == 0) rowoff[(int64_t)pl * nb + y] = cur[y];
+  }
+  if (q == 0 && pl == nb - 1 && tid == 0) rowoff[(int64_t)nb * nb] = phoff[(int64_t)nb * B];
+  // this thread's particles and keys of the next tile, loaded one tile ahead
+  float4 nv[kSortPer];
+  int nk[kSortPer];
+  const uint32_t total = phoff[(int64_t)nb * B];
+  load_row_tile(tmp, rowkey, lo, hi, tid, nv, nk);
+  for (uint32_t t0 = lo; t0 < hi; t0 += kSortTile) {
+    float4 v[kSortPer];
+    int key[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      v[j] = nv[j];
+      key[j] = nk[j];
+    }
+    if (t0 + kSortTile < hi) load_row_tile(tmp, rowkey, t0 + kSortTile, hi, tid, nv, nk);
+    __syncthreads();  // the previous tile's copy-out is done (and cur is set)
+    for (int k = tid; k < nb; k += kSortThreads) tcnt[k] = 0u;
+    __syncthreads();
+    uint32_t rank[kSortPer];
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) rank[j] = key[j] >= 0 ? atomicAdd(&tcnt[key[j]], 1u) : 0u;
+    __syncthreads();
+    for (int k = tid; k < nb; k += kSortThreads) {
+      gb[k] = cur[k];
+      cur[k] += tcnt[k];
+    }
+    const uint32_t ntile = block_scan_lds<kSortThreads>(tcnt, nb);
+#pragma unroll
+    for (int j = 0; j < kSortPer; ++j) {
+      if (key[j] >= 0) {
+        const uint32_t lp = tcnt[key[j]] + rank[j];
+        stage[lp] = v[j];
+        skey[lp] = (uint16_t)key[j];
+      }
+    }
+    __syncthreads();
+    for (uint32_t lp = tid; lp < ntile; lp += kSortThreads) {
+      const int k = skey[lp];
+      const uint32_t dst = gb[k] + (lp - tcnt[k]);
+      if (dst < total) sorted[dst] = stage[lp];
+    }
   }
 }
 
@@ -399,19 +570,24 @@ hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& r
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
   hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(256), 0, s, ph, nph, bsum, ph);
   float4* tmp = at<float4>(ws, p.off_tmp);
+  uint16_t* rowkey = at<uint16_t>(ws, p.off_rowkey);
+  const size_t shS = staged_lds_bytes(p.N);
   if (p.assign == PK_CIC)
-    hipLaunchKernelGGL(plane_scatter_kernel<PK_CIC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph,
-                       at<const double>(ws, p.off_scalars), tmp);
+    hipLaunchKernelGGL(plane_scatter_kernel<PK_CIC>, dim3(B), dim3(kSortThreads), shS, s, gal, ran, g, per, ph,
+                       at<const double>(ws, p.off_scalars), tmp, rowkey);
   else
-    hipLaunchKernelGGL(plane_scatter_kernel<PK_TSC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph,
-                       at<const double>(ws, p.off_scalars), tmp);
-  const size_t shB = sizeof(uint32_t) * 2 * p.N;
-  if (p.assign == PK_CIC)
-    hipLaunchKernelGGL(row_sort_kernel<PK_CIC>, dim3(p.N), dim3(1024), shB, s, tmp, ph, B, g,
-                       at<float4>(ws, p.off_sorted), at<uint32_t>(ws, p.off_rowoff));
-  else
-    hipLaunchKernelGGL(row_sort_kernel<PK_TSC>, dim3(p.N), dim3(1024), shB, s, tmp, ph, B, g,
-                       at<float4>(ws, p.off_sorted), at<uint32_t>(ws, p.off_rowoff));
+    hipLaunchKernelGGL(plane_scatter_kernel<PK_TSC>, dim3(B), dim3(kSortThreads), shS, s, gal, ran, g, per, ph,
+                       at<const double>(ws, p.off_scalars), tmp, rowkey);
+  uint32_t* rh = at<uint32_t>(ws, p.off_rowhist);
+  hipLaunchKernelGGL(row_hist_kernel, dim3(kRowParts, p.N), dim3(kSortThreads), sizeof(uint32_t) * p.N, s, rowkey, ph,
+                     B, p.N, rh);
+  const int64_t nrh = (int64_t)p.N * p.N * kRowParts;
+  const int nbr = (int)((nrh + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nbr), dim3(256), 0, s, rh, nrh, bsum);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nbr);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nbr), dim3(256), 0, s, rh, nrh, bsum, rh);
+  hipLaunchKernelGGL(row_sort_kernel, dim3(kRowParts, p.N), dim3(kSortThreads), shS, s, tmp, rowkey, ph, B, p.N, rh,
+                     at<float4>(ws, p.off_sorted), at<uint32_t>(ws, p.off_rowoff));
   return hipGetLastError();
 }
 
