@@ -103,6 +103,10 @@ def make_workload(name):
         gal, ran, cfg = catalogs.clustered_rsd_512()
         desc = ("lognormal RSD mock, 512^3 field, L=2500 Mpc/h at 2000 Mpc/h, nbar=3e-4, f=0.75, b=2, "
                 "20x randoms, FKP P0=1e4; CIC 512^3, ell=0,2,4, 128 bins of 2 k_f")
+    elif name == "desi_1024":
+        gal, ran, cfg = catalogs.desi_scale_1024_device()
+        desc = ("lognormal RSD mock made on the GPU, 1024^3 field, L=4000 Mpc/h at 3000 Mpc/h, nbar=4.69e-4, "
+                "f=0.75, b=2, 20x randoms, FKP P0=1e4; TSC 1024^3, ell=0,2,4 (22 grids), 256 bins of 2 k_f")
     elif name == "tiny_32":
         gal, ran, cfg = catalogs.tiny_plain()
         desc = "2000 uniform galaxies + 20000 randoms, 1000 Mpc/h cube at 1500 Mpc/h; CIC 32^3, ell=0,2,4"
@@ -236,12 +240,13 @@ def main():
     log("generated %d galaxies + %d randoms in %.1f s" % (gal.n, ran.n, time.perf_counter() - t))
     torch.cuda.set_device(0)
     torch.cuda.synchronize()
+    on_device = isinstance(gal, pk.DeviceCatalog)
     t = time.perf_counter()
-    g = pk.DeviceCatalog.from_host(gal)
-    r = pk.DeviceCatalog.from_host(ran)
+    g = gal if on_device else pk.DeviceCatalog.from_host(gal)
+    r = ran if on_device else pk.DeviceCatalog.from_host(ran)
     torch.cuda.synchronize()
     h2d_s = time.perf_counter() - t
-    h2d_bytes = 20 * (gal.n + ran.n)
+    h2d_bytes = 0 if on_device else 20 * (gal.n + ran.n)
     ws = pk.Workspace()
     log("workspace %.2f GB" % (native.workspace_size(cfg, gal.n, ran.n) / 1e9))
 
@@ -270,7 +275,7 @@ def main():
     value = 1e3 / ms_per_step
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not on_device:
         log("timing the FP64 oracle on a bounded sample")
         cpu = cpu_baseline(gal, ran, cfg)
         log("oracle sample took %.1f s" % cpu.pop("measured_s"))
@@ -296,7 +301,7 @@ def main():
                      "kernel_ms": stage_ms[dom], "algorithmic_bytes": byts[dom]},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stages_GBps": stage_gbs,
-        "h2d_GBps": h2d_bytes / h2d_s / 1e9,
+        "h2d_GBps": (h2d_bytes / h2d_s / 1e9) if h2d_bytes else None,
         "cpu_baseline": cpu,
         "P_check": {"P0_bin1": res["P0"][1], "P2_bin1": res["P2"][1], "P4_bin1": res["P4"][1]},
     }

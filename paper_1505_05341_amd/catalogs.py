@@ -178,6 +178,18 @@ def clustered_rsd_512(seed=2, N_field=512, N=512, **cfg_kw):
     return gal, ran, config_dict(N, box_min, 2500.0, **kw)
 
 
+def desi_scale_1024_device(seed=3, N_field=1024, N=1024, **cfg_kw):
+    """DESI-scale single catalogue, made on the GPU: lognormal RSD mock (same power law,
+    f = 0.75, b = 2) on a 1024^3 field, L = 4000 Mpc/h at 3000 Mpc/h, nbar = 4.6875e-4
+    (about 3e7 galaxies), 20x randoms (about 6e8), FKP P0 = 1e4; TSC on 1024^3, all 22
+    LOS-weighted grids (ell = 0, 2, 4), bins of width 2 k_f. Returns device catalogues."""
+    gal, ran, box_min = lognormal_rsd_device(N_field=N_field, L=4000.0, center=(0.0, 0.0, 3000.0),
+                                             nbar=3.0e7 / 4000.0 ** 3, seed=seed, ran_factor=20.0)
+    kw = dict(assign=3, ell_max=4, dn=2)
+    kw.update(cfg_kw)
+    return gal, ran, config_dict(N, box_min, 4000.0, **kw)
+
+
 def small_clustered(N=64, seed=7, L=600.0, nbar=1.0e-3, ran_factor=10.0, N_field=None, **cfg_kw):
     """Scaled-down version of the clustered RSD mock (same recipe, small box) for parity tests."""
     gal, ran, box_min = lognormal_rsd(N_field=N_field or N, L=L, center=(0.0, 0.0, 1.2 * L),

@@ -49,23 +49,30 @@ __device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&
   m[17] = yy * yy; m[18] = yy * yz; m[19] = yy * zz; m[20] = yz * zz; m[21] = zz * zz;
 }
 
-constexpr int XTHREADS = 512;
-constexpr int XCHUNK = 1024;   // particles per LDS chunk
-constexpr int XPER = XCHUNK / XTHREADS;  // particles per thread per chunk
+// Block geometry: 512 threads and chunks of 1024 particles up to N = 512; at N = 1024 one
+// block of 1024 threads (one cell per thread, all 22 grids in one block, so the particle
+// work is done once per target row) and chunks of 2048.
+template <int N>
+struct XGeom {
+  static constexpr int NT = N >= 1024 ? 1024 : 512;      // threads
+  static constexpr int CHUNK = N >= 1024 ? 2048 : 1024;  // particles per LDS chunk
+  static constexpr int PER = CHUNK / NT;                  // particles per thread per chunk
+};
 
 // Bytes of the gather-phase LDS area: pa float4[XCHUNK] (fx, w' W_y W_z, rx, ry),
 // pr float[XCHUNK] (rz), pix uint16[XCHUNK] (base cell), perm uint16[XCHUNK],
 // cnt uint32[N] (counts, then cursors), st uint32[N + 1] (first particle of each cell).
 template <int N>
 constexpr size_t gather_lds_bytes() {
-  return (size_t)XCHUNK * (16 + 4 + 2 + 2) + (size_t)N * 4 + (size_t)(N + 1) * 4;
+  return (size_t)XGeom<N>::CHUNK * (16 + 4 + 2 + 2) + (size_t)N * 4 + (size_t)(N + 1) * 4;
 }
 
 // Exclusive scan of cnt[0, N) into st[0, N] (st[N] = total); cnt[i] = st[i] on exit.
 template <int N>
 __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
-  constexpr int PER = (N + XTHREADS - 1) / XTHREADS;
-  __shared__ uint32_t wsum[XTHREADS / 64];
+  constexpr int NT = XGeom<N>::NT;
+  constexpr int PER = (N + NT - 1) / NT;
+  __shared__ uint32_t wsum[NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   uint32_t v[PER];
   uint32_t loc = 0;
@@ -94,17 +101,18 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
     }
     ex += v[j];
   }
-  if (tid == XTHREADS - 1) st[N] = ex;
+  if (tid == NT - 1) st[N] = ex;
   __syncthreads();
 }
 
 // Gathers rows G0 .. G0+NG of the block's target row into LDS rows[g - G0][x]
 // (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
-template <int N, int ASSIGN, int G, int G0, int NG, int NP, int S = (ASSIGN == PK_CIC ? 2 : 3)>
+template <int N, int ASSIGN, int G, int G0, int NG, int NP, bool OV, int S = (ASSIGN == PK_CIC ? 2 : 3)>
 __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict__ sorted, const uint32_t (&beg)[S * S],
                                             const uint32_t (&pre)[S * S + 1], const XArgs& a) {
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
-  constexpr int CPT = (N + XTHREADS - 1) / XTHREADS;  // target cells per thread
+  constexpr int NT = XGeom<N>::NT, XCHUNK = XGeom<N>::CHUNK, XPER = XGeom<N>::PER;
+  constexpr int CPT = (N + NT - 1) / NT;  // target cells per thread
   char* base = reinterpret_cast<char*>(lds);
   float4* pa = reinterpret_cast<float4*>(base);
   float* pr = reinterpret_cast<float*>(base + XCHUNK * 16);
@@ -115,12 +123,19 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   const int tid = threadIdx.x;
   // FP32 register sums; the order in which a cell's particles arrive is set by atomics
   // in the sorts, so repeated runs differ at the FP32 rounding level of a cell
-  float acc[CPT][NG];
+  // OV (one visit): each thread owns base cells and adds each particle once to the S target
+  // cells of its stencil, keeping one set of sums per stencil offset (S x more registers,
+  // S x fewer particle visits); otherwise each thread owns target cells and gathers from
+  // the S base cells that reach it.
+  constexpr int NS = OV ? S : 1;
+  float acc[CPT][NS][NG];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int g = 0; g < NG; ++g) acc[c][g] = 0.0f;
-  for (int i = tid; i < N; i += XTHREADS) cnt[i] = 0u;
+    for (int o = 0; o < NS; ++o)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[c][o][g] = 0.0f;
+  for (int i = tid; i < N; i += NT) cnt[i] = 0u;
   __syncthreads();
   const uint32_t total = pre[S * S];
   for (uint32_t c0 = 0; c0 < total; c0 += XCHUNK) {
@@ -130,7 +145,7 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     int sv[XPER];
 #pragma unroll
     for (int j = 0; j < XPER; ++j) {
-      const int i = tid + j * XTHREADS;
+      const int i = tid + j * NT;
       sv[j] = 0;
       if (i < n) {
         const uint32_t f = c0 + i;
@@ -148,7 +163,7 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     }
 #pragma unroll
     for (int j = 0; j < XPER; ++j) {
-      const int i = tid + j * XTHREADS;
+      const int i = tid + j * NT;
       if (i >= n) continue;
       const float4 q = qv[j];
       const int oy = O0 + sv[j] % S, oz = O0 + sv[j] / S;
@@ -174,28 +189,47 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     __syncthreads();
     // 2. counting sort of the chunk by base cell
     scan_counts<N>(cnt, st);
-    for (int i = tid; i < n; i += XTHREADS) {
+    for (int i = tid; i < n; i += NT) {
       const uint32_t pos = atomicAdd(&cnt[pix[i]], 1u);
       perm[pos] = (uint16_t)i;
     }
     __syncthreads();
-    // 3. gather: target cell x receives from base cells x - O0 - o with stencil offset O0 + o
+    // 3. gather
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      const int x = tid + c * XTHREADS;
+      const int x = tid + c * NT;
       if (x < N) {
-#pragma unroll
-        for (int o = 0; o < S; ++o) {
-          const int sc = (x - O0 - o) & (N - 1);
-          const uint32_t k1 = st[sc + 1];
-          for (uint32_t k = st[sc]; k < k1; ++k) {
+        if (OV) {
+          // each particle of base cell x, once: stencil offset o reaches cell x + O0 + o
+          const uint32_t k1 = st[x + 1];
+          for (uint32_t k = st[x]; k < k1; ++k) {
             const int i = perm[k];
             const float4 p = pa[i];
-            const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
+            float wo[S];
+#pragma unroll
+            for (int o = 0; o < S; ++o) wo[o] = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
             float m[G];
             monomials<G>(p.z, p.w, pr[i], m);
 #pragma unroll
-            for (int g = 0; g < NG; ++g) acc[c][g] += w * m[G0 + g];
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+              for (int o = 0; o < NS; ++o) acc[c][o][g] += wo[o] * m[G0 + g];
+          }
+        } else {
+          // target cell x receives from base cells x - O0 - o with stencil offset O0 + o
+#pragma unroll
+          for (int o = 0; o < S; ++o) {
+            const int sc = (x - O0 - o) & (N - 1);
+            const uint32_t k1 = st[sc + 1];
+            for (uint32_t k = st[sc]; k < k1; ++k) {
+              const int i = perm[k];
+              const float4 p = pa[i];
+              const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
+              float m[G];
+              monomials<G>(p.z, p.w, pr[i], m);
+#pragma unroll
+              for (int g = 0; g < NG; ++g) acc[c][0][g] += w * m[G0 + g];
+            }
           }
         }
         cnt[x] = 0u;  // ready for the next chunk (only this thread touches cell x here)
@@ -203,15 +237,34 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     }
     __syncthreads();
   }
-  // rows alias the gather area: all gathers are done (barrier above)
+  // rows alias the gather area (all gathers are done: barrier above). With OV the sums of
+  // the own cell (offset -O0) are stored first and each other offset is added in a phase
+  // of its own, so every cell has a single writer in each phase.
+  constexpr int OWN = OV ? -O0 : 0;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int x = tid + c * XTHREADS;
+    const int x = tid + c * NT;
     if (x < N) {
 #pragma unroll
-      for (int g = 0; g < NG; ++g) lds[g * N + x] = acc[c][g];
+      for (int g = 0; g < NG; ++g) lds[g * N + x] = acc[c][OWN][g];
 #pragma unroll
       for (int g = NG; g < 2 * NP; ++g) lds[g * N + x] = 0.0f;
+    }
+  }
+  if (OV) {
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      if (o == OWN) continue;
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int x = tid + c * NT;
+        if (x < N) {
+          const int xt = (x + O0 + o) & (N - 1);
+#pragma unroll
+          for (int g = 0; g < NG; ++g) lds[g * N + xt] += acc[c][o][g];
+        }
+      }
     }
   }
   __syncthreads();
@@ -223,9 +276,13 @@ struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
 
-// 6 waves per SIMD (3 blocks of 512 threads per CU, as the LDS allows): <= 80 VGPRs.
+// Waves per SIMD the registers are budgeted for: 6 (3 blocks of 512 threads per CU, as
+// the LDS allows; <= 80 VGPRs) up to N = 512, 4 (one block of 1024 threads) at 1024.
+template <int N>
+constexpr int xpass_waves() { return N >= 1024 ? 4 : 6; }
+
 template <int N, int ASSIGN, int ELL, int SPLIT>
-__global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
+__global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
   constexpr int G = num_grids(ELL);
   constexpr int GB = (G + SPLIT - 1) / SPLIT;
@@ -233,7 +290,7 @@ __global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))
   constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
   using F = Fft<N>;
-  static_assert(NP * F::T <= XTHREADS, "row pairs do not fit the block");
+  static_assert(NP * F::T <= XGeom<N>::NT, "row pairs do not fit the block");
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
@@ -258,11 +315,11 @@ __global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))
     pre[s + 1] = pre[s] + (rowoff[r + 1] - beg[s]);
   }
   if (SPLIT == 1) {
-    gather_rows<N, ASSIGN, G, 0, G, NP>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, 0, G, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
   } else if (part == 0) {
-    gather_rows<N, ASSIGN, G, 0, GB, NP>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, 0, GB, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
   } else {
-    gather_rows<N, ASSIGN, G, GB, G - GB, NP>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, GB, G - GB, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
   }
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
@@ -305,12 +362,14 @@ __global__ __launch_bounds__(XTHREADS) __attribute__((amdgpu_waves_per_eu(6, 8))
 template <int N, int ASSIGN, int ELL>
 static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
   constexpr int G = num_grids(ELL);
-  constexpr int SPLIT = (N >= 1024 && G > 16) ? 2 : 1;
+  constexpr int SPLIT = 1;
   constexpr int GB = (G + SPLIT - 1) / SPLIT;
   constexpr int NP = (GB + 1) / 2;
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
   const size_t shmem = rows > gather_lds_bytes<N>() ? rows : gather_lds_bytes<N>();
-  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, N, SPLIT), dim3(XTHREADS), shmem, s,
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL, SPLIT>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, N, SPLIT), dim3(XGeom<N>::NT), shmem, s,
                      at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
                      at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);
   return hipGetLastError();

@@ -1,6 +1,6 @@
-"""Parity at the full size of the benchmark workload (clustered RSD mock, 9.9e7
-particles, CIC on 512^3, ell = 0, 2, 4, 128 bins of 2 k_f), in the launch configuration
-bench.py times. The oracle cannot redo the whole 22-grid estimator at this size in a
+"""Parity at the full size of the benchmark workloads, in the launch configurations
+bench.py times: the clustered RSD mock (9.9e7 particles, CIC on 512^3, ell = 0, 2, 4,
+128 bins of 2 k_f) and the DESI-scale catalogue (6.3e8 particles, TSC on 1024^3). The oracle cannot redo the whole 22-grid estimator at this size in a
 test, so two checks it can afford are made instead:
 
 * sampled outputs: rows of the x-transformed LOS-weighted grids (the fused assignment
@@ -33,6 +33,7 @@ TOL = 1e-5
 # (observed 1e-7 to 1.5e-5), on top of a few eps_32 from the cell sums and the radix
 # stages. A lost or misplaced particle would show as ~1 / 1500 ~ 7e-4 of l1.
 XTOL = 4e-5
+XTOL_1024 = 8e-5  # the same bound with u up to 1024
 
 
 @pytest.fixture(scope="module")
@@ -140,3 +141,48 @@ def test_plane_parallel_full_size(workload):
         e = np.max(np.abs(got["P%d" % ell][ok] - ref[ell][ok]) / raw[ok])
         print("ell", ell, "e_l %.2e" % e, flush=True)
         assert e <= TOL, (ell, e)
+
+
+@pytest.mark.parametrize("assign", [3, 2])
+def test_sampled_x_rows_desi_1024(assign):
+    """DESI-scale catalogue made on the GPU (3e7 galaxies + 6e8 randoms, 1024^3, 22
+    grids; TSC as in the workload, and CIC): sampled x-transformed rows against the
+    oracle. Only the particles whose stencil can reach a sampled row are copied to the
+    host (a superset of those the oracle row function keeps)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1505_05341_amd as pk
+    from paper_1505_05341_amd import native
+    t = time.time()
+    gal, ran, cfg = catalogs.desi_scale_1024_device(assign=assign)
+    print("DESI-scale workload: %d galaxies + %d randoms (%.1f s)" % (gal.n, ran.n, time.time() - t), flush=True)
+    ws, layout = pk.stage_xgrids(gal, ran, cfg)
+    c = est.Config(**cfg)
+    N = c.N
+    alpha, I, S = est.catalogue_scalars(gal.w.cpu().numpy(), ran.w.cpu().numpy(), gal.nbar.cpu().numpy(),
+                                        ran.nbar.cpu().numpy())
+    bmin = torch.tensor(c.box_min, dtype=torch.float32, device="cuda")
+
+    def near(cat, iy, iz):
+        # FP32 cell estimate with a one-cell margin: a superset of the TSC stencil's reach
+        j = torch.floor((cat.pos[:, 1:] - bmin[1:]) * (N / c.L) + 0.5).to(torch.int32)
+        sel = (((iy - j[:, 0]) % N + 2) % N <= 4) & (((iz - j[:, 1]) % N + 2) % N <= 4)
+        return cat.pos[sel].cpu().numpy().astype(np.float64), cat.w[sel].cpu().numpy()
+
+    rng = np.random.default_rng(13)
+    rows = [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(3)] + [(0, N - 1)]
+    for iy, iz in rows:
+        gp, gw = near(gal, iy, iz)
+        rp, rw = near(ran, iy, iz)
+        sub_pos = np.concatenate([gp, rp])
+        sub_w = est.signed_weights(gw, rw, alpha)
+        l1 = est.x_transformed_row(sub_pos, np.abs(sub_w), c, (0, 0, 0), iy, iz)[0].real
+        for m in (0, 6, 21):
+            kx = layout[m][1]
+            X = pk.xgrid_view(ws, layout, m, N)
+            got = X[iz, iy].cpu().numpy()
+            got = got[:, 0] + 1j * got[:, 1]
+            ref = est.x_transformed_row(sub_pos, sub_w, c, native.monomial(m), iy, iz)[:kx]
+            err = np.max(np.abs(got - ref)) / l1
+            print("row", (iy, iz), "grid", m, "particles", len(sub_pos), "err %.2e" % err, flush=True)
+            assert err < XTOL_1024, (iy, iz, m, err)
