@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mocks", type=int, default=256, help="ensemble size for --workload batch")
     ap.add_argument("--lanes", type=int, default=2, help="concurrent lanes for --workload batch")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default column-transform schedules instead of autotuning them first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -250,6 +252,11 @@ def main():
     ws = pk.Workspace()
     log("workspace %.2f GB" % (native.workspace_size(cfg, gal.n, ran.n) / 1e9))
 
+    schedule = native.get_schedule(cfg["N"], cfg["ell_max"])
+    if not args.no_autotune:
+        t = time.perf_counter()
+        schedule = pk.autotune(g, r, cfg, reps=3, workspace=ws)
+        log("autotuned column schedules (y, z values per thread): %s in %.2f s" % (schedule, time.perf_counter() - t))
     for i in range(args.warmup):
         pk.pk_multipoles(g, r, cfg, ws)
         log("warmup", i)
@@ -295,7 +302,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "grid": cfg["N"], "n_gal": gal.n, "n_ran": ran.n,
                    "ell_max": cfg["ell_max"], "assign": "CIC" if cfg["assign"] == 2 else "TSC",
-                   "nbins": cfg["nbins"], "dn": cfg["dn"]},
+                   "nbins": cfg["nbins"], "dn": cfg["dn"],
+                   "fft_schedule": {"y_values_per_thread": schedule[0], "z_values_per_thread": schedule[1]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
                      "kernel_ms": stage_ms[dom], "algorithmic_bytes": byts[dom]},

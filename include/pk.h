@@ -162,6 +162,23 @@ pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
                           size_t* offset, int32_t* kx_count);
 
+/* Schedules of the column transforms (the FFTs along y and along z): the values each
+ * thread holds, 16 (radices 16, 8, 4 at N = 512: fewer threads per transform) or 8
+ * (radices 8, 8, 8: half the registers). A process-wide table keyed by (N, ell_max),
+ * default 16 for both passes, read when a call plans its work (not thread-safe against
+ * concurrent changes). Both schedules compute the same transform; results agree to FP32
+ * rounding. PK_EINVAL for an unsupported N or ell_max or values other than 8 and 16. */
+pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t z_values);
+pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t* z_values);
+
+/* Autotuner of those schedules: runs pk_multipoles once on the given inputs (same
+ * arguments, workspace and errors), then times `reps` launches of every schedule of the
+ * y pass and of the z pass on that data with HIP events on hip_stream, stores the
+ * fastest pair in the table for (cfg->N, cfg->ell_max) and returns it. Synchronous. */
+pk_status pk_autotune(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                      size_t workspace_bytes, int32_t reps, int32_t* y_values, int32_t* z_values,
+                      void* hip_stream);
+
 /* Stage timing, for measurement. While enabled (process-wide, not thread-safe), each
  * pk_multipoles / pk_multipoles_async call records HIP events on its stream around its
  * stages: 0 workspace init, 1 catalogue scalars, 2 row sort, 3 LOS assignment + x FFT,

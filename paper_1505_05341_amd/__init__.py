@@ -4,6 +4,6 @@ A from-scratch HIP implementation of the FFT-based Yamamoto estimator of Bianchi
 Gil-Marin, Ruggeri & Percival (2015). The C interface is include/pk.h (libpk.so);
 this package is its Python binding plus the seeded synthetic catalogue generators.
 """
-from .native import PkError, load  # noqa: F401
-from .api import (DeviceCatalog, Workspace, pk_multipoles, pk_multipoles_batch, stage_xgrids,  # noqa: F401
-                  xgrid_view)
+from .native import PkError, get_schedule, load, set_schedule  # noqa: F401
+from .api import (DeviceCatalog, Workspace, autotune, pk_multipoles, pk_multipoles_batch,  # noqa: F401
+                  stage_xgrids, xgrid_view)

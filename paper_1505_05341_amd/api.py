@@ -161,3 +161,17 @@ def xgrid_view(ws, layout, m, N):
     nbytes = N * N * kx * 8
     raw = ws[off:off + nbytes]
     return raw.view(torch.float32).view(N, N, kx, 2)
+
+
+def autotune(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, reps: int = 3, workspace: Workspace | None = None):
+    """Times both column-transform schedules of the y and z passes on these inputs, keeps
+    the fastest for (N, ell_max) in the library's table and returns (y_values, z_values)."""
+    lib = native.load()
+    c = native.make_config(cfg)
+    nbytes = native.workspace_size(cfg, gal.n, ran.n)
+    ws = (workspace or Workspace()).get(nbytes)
+    y, z = ctypes.c_int32(), ctypes.c_int32()
+    native.check(lib.pk_autotune(ctypes.byref(c), ctypes.byref(gal.c_struct()), ctypes.byref(ran.c_struct()),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(reps), ctypes.byref(y),
+                                 ctypes.byref(z), native.current_stream()))
+    return int(y.value), int(z.value)

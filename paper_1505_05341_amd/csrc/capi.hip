@@ -35,6 +35,19 @@ static bool supported_N(int N) {
   return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
 }
 
+// Schedules of the column transforms (values per thread of the y and z passes), per
+// (N, ell_max): set by pk_set_schedule or the autotuner; 0 = not set, meaning 16.
+struct Schedule {
+  int y, z;
+};
+static Schedule g_sched[11][3];
+
+static int log2_of(int N) {
+  int l = 0;
+  while ((1 << l) < N) ++l;
+  return l;
+}
+
 pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* plan, const char** why) {
   static const char* msg = "";
   *why = msg;
@@ -90,6 +103,9 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.H_group_stride = (size_t)reg;
   p.z_items = items;
   p.z_blocks = (int)(items < 512 ? items : 512);
+  const Schedule sc = g_sched[log2_of(p.N)][p.ell_max / 2];
+  p.col_e[0] = sc.y ? sc.y : 16;
+  p.col_e[1] = sc.z ? sc.z : 16;
 
   // groups (n, c) and their members (grid index, a, b, multinomial weight)
   GroupTable& gt = p.groups;
@@ -289,6 +305,89 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
   out->alpha = tail[0];
   out->I = tail[1];
   out->S = tail[2];
+  return PK_OK;
+}
+
+// ------------------------------------------------------------------- FFT schedules
+
+static bool schedule_key_ok(int32_t N, int32_t ell_max) {
+  return supported_N(N) && (ell_max == 0 || ell_max == 2 || ell_max == 4);
+}
+
+pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t z_values) {
+  if (!schedule_key_ok(N, ell_max)) return fail(PK_EINVAL, "unsupported N or ell_max");
+  if ((y_values != 8 && y_values != 16) || (z_values != 8 && z_values != 16))
+    return fail(PK_EINVAL, "values per thread must be 8 or 16");
+  g_sched[log2_of(N)][ell_max / 2] = Schedule{y_values, z_values};
+  return PK_OK;
+}
+
+pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t* z_values) {
+  if (!schedule_key_ok(N, ell_max)) return fail(PK_EINVAL, "unsupported N or ell_max");
+  if (!y_values || !z_values) return fail(PK_EINVAL, "null output pointer");
+  const Schedule sc = g_sched[log2_of(N)][ell_max / 2];
+  *y_values = sc.y ? sc.y : 16;
+  *z_values = sc.z ? sc.z : 16;
+  return PK_OK;
+}
+
+// Average duration in ms of `reps` launches of one pass with column schedule `e`.
+static pk_status time_pass(Plan p, int which, int e, char* ws, int reps, hipStream_t s, hipEvent_t a, hipEvent_t b,
+                           float* ms) {
+  p.col_e[which] = e;
+  hipError_t err = which == 0 ? launch_ypass(p, ws, s) : launch_zpass(p, ws, s);  // warm-up
+  if (err != hipSuccess) return hip_fail(err, "autotune warm-up");
+  if ((err = hipEventRecord(a, s)) != hipSuccess) return hip_fail(err, "event record");
+  for (int r = 0; r < reps; ++r) {
+    err = which == 0 ? launch_ypass(p, ws, s) : launch_zpass(p, ws, s);
+    if (err != hipSuccess) return hip_fail(err, "autotune launch");
+  }
+  if ((err = hipEventRecord(b, s)) != hipSuccess) return hip_fail(err, "event record");
+  if ((err = hipEventSynchronize(b)) != hipSuccess) return hip_fail(err, "event synchronize");
+  if ((err = hipEventElapsedTime(ms, a, b)) != hipSuccess) return hip_fail(err, "event time");
+  *ms /= (float)reps;
+  return PK_OK;
+}
+
+pk_status pk_autotune(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                      size_t workspace_bytes, int32_t reps, int32_t* y_values, int32_t* z_values, void* hip_stream) {
+  if (reps < 1) return fail(PK_EINVAL, "reps must be >= 1");
+  if (!y_values || !z_values) return fail(PK_EINVAL, "null output pointer");
+  pk_result dummy;
+  memset(&dummy, 0, sizeof(dummy));
+  // one full run validates the inputs and leaves the grids the passes read in the workspace
+  pk_status st = pk_multipoles(cfg, gal, ran, workspace, workspace_bytes, &dummy, hip_stream);
+  if (st != PK_OK) return st;
+  Plan p;
+  st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
+  if (st != PK_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t err;
+  if ((err = hipEventCreate(&a)) != hipSuccess) return hip_fail(err, "event create");
+  if ((err = hipEventCreate(&b)) != hipSuccess) {
+    hipEventDestroy(a);
+    return hip_fail(err, "event create");
+  }
+  const int cand[2] = {16, 8};
+  int best[2] = {16, 16};
+  for (int which = 0; which < 2 && st == PK_OK; ++which) {
+    float tbest = 0.0f;
+    for (int k = 0; k < 2 && st == PK_OK; ++k) {
+      float ms = 0.0f;
+      st = time_pass(p, which, cand[k], static_cast<char*>(workspace), reps, s, a, b, &ms);
+      if (st == PK_OK && (k == 0 || ms < tbest)) {
+        tbest = ms;
+        best[which] = cand[k];
+      }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (st != PK_OK) return st;
+  g_sched[log2_of(p.N)][p.ell_max / 2] = Schedule{best[0], best[1]};
+  *y_values = best[0];
+  *z_values = best[1];
   return PK_OK;
 }
 

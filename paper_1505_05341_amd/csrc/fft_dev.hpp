@@ -66,25 +66,35 @@ struct Dft<2> {
   }
 };
 
-// Radices of each supported length (largest first, so E = radix(0)).
-template <int N> struct Radices;
-template <> struct Radices<8>    { static constexpr int NS = 2, R0 = 4,  R1 = 2,  R2 = 1; };
-template <> struct Radices<16>   { static constexpr int NS = 2, R0 = 4,  R1 = 4,  R2 = 1; };
-template <> struct Radices<32>   { static constexpr int NS = 2, R0 = 8,  R1 = 4,  R2 = 1; };
-template <> struct Radices<64>   { static constexpr int NS = 2, R0 = 8,  R1 = 8,  R2 = 1; };
-template <> struct Radices<128>  { static constexpr int NS = 2, R0 = 16, R1 = 8,  R2 = 1; };
-template <> struct Radices<256>  { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 1; };
-template <> struct Radices<512>  { static constexpr int NS = 3, R0 = 16, R1 = 8,  R2 = 4; };
-template <> struct Radices<1024> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4; };
+// Radices of each supported length (largest first, so E = radix(0)), for at most EMAX
+// values per thread: 16 (fewer, larger stages; fewer threads per transform) or 8 (half
+// the registers per thread, twice the threads).
+template <int N, int EMAX> struct Radices;
+template <> struct Radices<8, 16>    { static constexpr int NS = 2, R0 = 4,  R1 = 2,  R2 = 1, R3 = 1; };
+template <> struct Radices<16, 16>   { static constexpr int NS = 2, R0 = 4,  R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Radices<32, 16>   { static constexpr int NS = 2, R0 = 8,  R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Radices<64, 16>   { static constexpr int NS = 2, R0 = 8,  R1 = 8,  R2 = 1, R3 = 1; };
+template <> struct Radices<128, 16>  { static constexpr int NS = 2, R0 = 16, R1 = 8,  R2 = 1, R3 = 1; };
+template <> struct Radices<256, 16>  { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
+template <> struct Radices<512, 16>  { static constexpr int NS = 3, R0 = 16, R1 = 8,  R2 = 4, R3 = 1; };
+template <> struct Radices<1024, 16> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
+template <> struct Radices<8, 8>     { static constexpr int NS = 2, R0 = 4,  R1 = 2,  R2 = 1, R3 = 1; };
+template <> struct Radices<16, 8>    { static constexpr int NS = 2, R0 = 4,  R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Radices<32, 8>    { static constexpr int NS = 2, R0 = 8,  R1 = 4,  R2 = 1, R3 = 1; };
+template <> struct Radices<64, 8>    { static constexpr int NS = 2, R0 = 8,  R1 = 8,  R2 = 1, R3 = 1; };
+template <> struct Radices<128, 8>   { static constexpr int NS = 3, R0 = 8,  R1 = 8,  R2 = 2, R3 = 1; };
+template <> struct Radices<256, 8>   { static constexpr int NS = 3, R0 = 8,  R1 = 8,  R2 = 4, R3 = 1; };
+template <> struct Radices<512, 8>   { static constexpr int NS = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
+template <> struct Radices<1024, 8>  { static constexpr int NS = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 2; };
 
-template <int N>
+template <int N, int EMAX = 16>
 struct Fft {
-  using Rd = Radices<N>;
+  using Rd = Radices<N, EMAX>;
   static constexpr int NS = Rd::NS;
   static constexpr int E = Rd::R0;   // values per thread
   static constexpr int T = N / E;    // threads per transform
-  static constexpr int radix(int s) { return s == 0 ? Rd::R0 : (s == 1 ? Rd::R1 : Rd::R2); }
-  static constexpr int span(int s) { return s == 0 ? 1 : (s == 1 ? Rd::R0 : Rd::R0 * Rd::R1); }  // Ns
+  static constexpr int radix(int s) { return s == 0 ? Rd::R0 : (s == 1 ? Rd::R1 : (s == 2 ? Rd::R2 : Rd::R3)); }
+  static constexpr int span(int s) { return s == 0 ? 1 : radix(s - 1) * span(s - 1); }  // Ns
   static constexpr int RL = radix(NS - 1);
 
   // Index read by value (q, r) of thread t at stage s.
@@ -131,13 +141,17 @@ struct Fft {
   __device__ __forceinline__ static void run(float2 (&d)[E], int t, const float2* __restrict__ tw, float2* lds,
                                              Slot slot, bool active = true) {
     if (active) stage<0>(d, t, tw);
-    if (NS > 1) {
+    if constexpr (NS > 1) {
       exchange<0>(d, t, lds, slot, active);
       if (active) stage<(NS > 1 ? 1 : 0)>(d, t, tw);
     }
-    if (NS > 2) {
+    if constexpr (NS > 2) {
       exchange<(NS > 2 ? 1 : 0)>(d, t, lds, slot, active);
       if (active) stage<(NS > 2 ? 2 : 0)>(d, t, tw);
+    }
+    if constexpr (NS > 3) {
+      exchange<(NS > 3 ? 2 : 0)>(d, t, lds, slot, active);
+      if (active) stage<(NS > 3 ? 3 : 0)>(d, t, tw);
     }
   }
 

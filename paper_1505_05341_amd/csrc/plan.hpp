@@ -83,6 +83,7 @@ struct Plan {
   int nkt;        // kx tiles
   int x_split;    // blocks per x row (grids split between them)
   int z_blocks;   // persistent blocks of the z pass
+  int col_e[2];   // values per thread of the column transforms of the y and z passes (8 or 16)
   int64_t z_items;
   GroupTable groups;
   TileTable tiles;

@@ -50,25 +50,34 @@ struct ColSlot {
 template <int N>
 constexpr int tile_cols() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }
 
-template <int N, int TK>
-__global__ __launch_bounds__(TK * Fft<N>::T) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
-                                                              const float2* __restrict__ tw, const YArgs a) {
-  using F = Fft<N>;
+// Column transforms come in two schedules, picked per plan (the autotuner times both):
+// EC = 16 values per thread (radices 16, 8, 4 at 512: fewer threads) or EC = 8 (radices
+// 8, 8, 8: half the registers). With EC = 8 the thread's row index is hidden from the
+// optimiser where it is used, so that the addresses derived from it are recomputed
+// instead of being held in registers across the loops (that would cost the occupancy the
+// smaller schedule is for); with EC = 16 the code is left to the optimiser.
+template <int EC>
+__device__ __forceinline__ int col_hide(int v) {
+  if constexpr (EC == 8) asm volatile("" : "+v"(v));
+  return v;
+}
+
+template <int N, int TK, int EC>
+__global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
+                                                                  const float2* __restrict__ tw, const YArgs a) {
+  using F = Fft<N, EC>;
   extern __shared__ float2 T[];
-  const int tid = threadIdx.x;
-  const int c = tid % TK, t = tid / TK;
+  const int tid0 = threadIdx.x;
   const int kt = blockIdx.x, z = blockIdx.y;
-  const int kx = kt * TK + c;
-  const float tx = (float)kx * (2.0f / N);
   const GroupTable& gt = *a.gt;
   const int M = a.tt->M[kt];
   const int64_t regoff = a.tt->regoff[kt];
   const int nslot = 2 * M + 1;
   const int Kx = a.Kx;
-  const ColSlot<TK> slot{c};
+  // the EC = 16 schedule keeps the ty of its values in registers
   float tyv[F::E];
 #pragma unroll
-  for (int e = 0; e < F::E; ++e) tyv[e] = (float)signed_freq<N>(F::out_index(t, e)) * (2.0f / N);
+  for (int e = 0; e < F::E; ++e) tyv[e] = (float)signed_freq<N>(F::out_index(tid0 / TK, e)) * (2.0f / N);
   const int ngroups = gt.ngroups;
   for (int g = 0; g < ngroups; ++g) {
     // Horner in ty over the members, whose powers of y run 0, 1, .., n - c:
@@ -78,19 +87,24 @@ __global__ __launch_bounds__(TK * Fft<N>::T) void ypass_kernel(const float2* __r
     for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
     const int cnt = gt.count[g];
     for (int s = cnt - 1; s >= 0; --s) {
+      const int tid = col_hide<EC>(tid0);
+      const int c = tid % TK, t = tid / TK;
+      const int kx = kt * TK + c;
       const int m = gt.grid[g][s];
       const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)z * N * Kx + kx;
       float2 d[F::E];
 #pragma unroll
       for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * Kx];
-      F::run(d, t, tw, T, slot);
-      const float fx = gt.coef[g][s] * ipow(tx, gt.a[g][s]);
+      F::run(d, t, tw, T, ColSlot<TK>{c});
+      const float fx = gt.coef[g][s] * ipow((float)kx * (2.0f / N), gt.a[g][s]);
 #pragma unroll
       for (int e = 0; e < F::E; ++e) {
-        acc[e].x = acc[e].x * tyv[e] + fx * d[e].x;
-        acc[e].y = acc[e].y * tyv[e] + fx * d[e].y;
+        const float ty = EC == 8 ? (float)signed_freq<N>(F::out_index(t, e)) * (2.0f / N) : tyv[e];
+        acc[e].x = acc[e].x * ty + fx * d[e].x;
+        acc[e].y = acc[e].y * ty + fx * d[e].y;
       }
     }
+    const int c = tid0 % TK, t = tid0 / TK;
     float2* __restrict__ dst = H + (size_t)g * a.h_group_stride + regoff + (size_t)z * nslot * TK + c;
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -109,10 +123,17 @@ static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s) {
   a.gt = at<const GroupTable>(ws, p.off_tables);
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
   const size_t shmem = (size_t)TK * N * sizeof(float2);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)shmem);
-  hipLaunchKernelGGL((ypass_kernel<N, TK>), dim3(p.nkt, N), dim3(TK * Fft<N>::T), shmem, s,
-                     at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
+  if (p.col_e[0] == 8) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 8>), dim3(p.nkt, N), dim3(TK * Fft<N, 8>::T), shmem, s,
+                       at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
+  } else {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 16>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 16>), dim3(p.nkt, N), dim3(TK * Fft<N, 16>::T), shmem, s,
+                       at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
+  }
   return hipGetLastError();
 }
 
@@ -148,22 +169,52 @@ __device__ __forceinline__ int isqrt_i(int n) {
   return s;
 }
 
-template <int N, int TK>
-__device__ __forceinline__ void zfft(const float2* __restrict__ col, int zstride, int c, int t, const float2* tw,
-                                     float2* T, float2 (&d)[Fft<N>::E]) {
-  using F = Fft<N>;
+template <int N, int TK, int EC>
+__device__ __forceinline__ void zfft(const float2* __restrict__ col, int zstride, int c, int t0, const float2* tw,
+                                     float2* T, float2 (&d)[Fft<N, EC>::E]) {
+  using F = Fft<N, EC>;
+  const int t = col_hide<EC>(t0);
 #pragma unroll
   for (int e = 0; e < F::E; ++e) d[e] = col[(size_t)F::in_index(t, e) * zstride];
   F::run(d, t, tw, T, ColSlot<TK>{c});
 }
 
-template <int N, int TK, int ELL>
-__global__ __launch_bounds__(TK * Fft<N>::T) void zpass_kernel(const float2* __restrict__ H, const float2* __restrict__ tw,
-                                                              const float* __restrict__ invw2,
-                                                              const float* __restrict__ alias,
-                                                              const double* __restrict__ scal, double* __restrict__ zpart,
-                                                              const ZArgs a) {
-  using F = Fft<N>;
+// acc <- acc tz + FFT_z[H_(n, c)] for c = CMAX .. 0 (Horner in tz over the z-power groups
+// first .. first + CMAX of degree n).
+template <int N, int TK, int EC, int CMAX>
+__device__ __forceinline__ void z_horner(const float2* base, int64_t gstride, int first, int zstride, int c, int t,
+                                         const float2* tw, float2* T, float2 (&acc)[Fft<N, EC>::E]) {
+  using F = Fft<N, EC>;
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
+  auto step = [&](int cz) {
+    float2 u[F::E];
+    zfft<N, TK, EC>(base + (size_t)(first + cz) * gstride, zstride, c, t, tw, T, u);
+    const int tt = col_hide<EC>(t);
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+      const float tz = (float)signed_freq<N>(F::out_index(tt, e)) * (2.0f / N);
+      acc[e].x = acc[e].x * tz + u[e].x;
+      acc[e].y = acc[e].y * tz + u[e].y;
+    }
+  };
+  if constexpr (EC == 8) {
+    // one transform at a time: unrolled, the loads of several would be hoisted together
+#pragma unroll 1
+    for (int cz = CMAX; cz >= 0; --cz) step(cz);
+  } else {
+    for (int cz = CMAX; cz >= 0; --cz) step(cz);
+  }
+}
+
+template <int N, int TK, int ELL, int EC>
+__global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float2* __restrict__ H,
+                                                                  const float2* __restrict__ tw,
+                                                                  const float* __restrict__ invw2,
+                                                                  const float* __restrict__ alias,
+                                                                  const double* __restrict__ scal,
+                                                                  double* __restrict__ zpart, const ZArgs a) {
+  using F = Fft<N, EC>;
   extern __shared__ __align__(16) char smem[];
   float2* T = reinterpret_cast<float2*>(smem);
   double* bins = reinterpret_cast<double*>(smem + (size_t)TK * N * sizeof(float2));
@@ -172,13 +223,6 @@ __global__ __launch_bounds__(TK * Fft<N>::T) void zpass_kernel(const float2* __r
   for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) bins[i] = 0.0;
   const double S = scal[kNoiseS];
   const float twoN = 2.0f / N;
-  int kzi[F::E];
-  float tzv[F::E];
-#pragma unroll
-  for (int e = 0; e < F::E; ++e) {
-    kzi[e] = F::out_index(t, e);
-    tzv[e] = (float)signed_freq<N>(kzi[e]) * twoN;
-  }
   for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
     int kt = 0;
     for (int k = 1; k < a.nkt; ++k) kt = item >= a.tt->item0[k] ? k : kt;
@@ -195,70 +239,54 @@ __global__ __launch_bounds__(TK * Fft<N>::T) void zpass_kernel(const float2* __r
     const double mu = kx == 0 ? 1.0 : 2.0;
 
     float2 a0[F::E];
-    zfft<N, TK>(base, zstride, c, t, tw, T, a0);
+    zfft<N, TK, EC>(base, zstride, c, t, tw, T, a0);
 
     float2 acc[F::E];
-    if (ELL >= 2) {
-#pragma unroll
-      for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
-      for (int cz = 2; cz >= 0; --cz) {  // Horner in tz: acc <- acc tz + FFT_z[H_(n,cz)]
-        float2 u[F::E];
-        zfft<N, TK>(base + (size_t)(1 + cz) * a.h_group_stride, zstride, c, t, tw, T, u);
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-          acc[e].x = acc[e].x * tzv[e] + u[e].x;
-          acc[e].y = acc[e].y * tzv[e] + u[e].y;
-        }
-      }
-    }
-    // pass 1: counts, |n|, Q0, Q2 (ell_max >= 2) and the noise
-#pragma unroll
-    for (int e = 0; e < F::E; ++e) {
-      const int kz = signed_freq<N>(kzi[e]);
-      const int n2 = n2xy + kz * kz;
-      const bool valid = n2 > 0 && n2 < a.K2;
-      const int b = valid ? isqrt_i(n2) / a.dn : 0;
-      float iw = 1.0f, noise_f = 1.0f;
-      if (a.compensate >= 1) iw = wxy * invw2[kzi[e]];
-      if (a.compensate == 2) noise_f = cxy * alias[kzi[e]] * iw;
-      const float2 z0 = a0[e];
-      const float q0 = (z0.x * z0.x + z0.y * z0.y) * iw;
-      double w4[4];
-      w4[0] = mu;
-      w4[1] = mu * (double)sqrtf((float)n2);
-      w4[2] = mu * (double)q0;
-      w4[3] = 0.0;
-      if (ELL >= 2) {
-        const float tz = tzv[e];
-        const float inv_t2 = 1.0f / (tx * tx + ty * ty + tz * tz);
-        const float2 A2 = acc[e];
-        w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
-      }
-      // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise
-      bin_add<4>(bins, b, valid, w4, 0);
-      double w1[1] = {mu * S * (double)noise_f};
-      bin_add<1>(bins, b, valid, w1, 5);
-    }
-    if (ELL >= 4) {
-#pragma unroll
-      for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
-      for (int cz = 4; cz >= 0; --cz) {  // Horner in tz: acc <- acc tz + FFT_z[H_(n,cz)]
-        float2 u[F::E];
-        zfft<N, TK>(base + (size_t)(4 + cz) * a.h_group_stride, zstride, c, t, tw, T, u);
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-          acc[e].x = acc[e].x * tzv[e] + u[e].x;
-          acc[e].y = acc[e].y * tzv[e] + u[e].y;
-        }
-      }
+    if (ELL >= 2) z_horner<N, TK, EC, 2>(base, a.h_group_stride, 1, zstride, c, t, tw, T, acc);
+    {
+      // pass 1: counts, |n|, Q0, Q2 (ell_max >= 2) and the noise
+      const int tt = col_hide<EC>(t);
 #pragma unroll
       for (int e = 0; e < F::E; ++e) {
-        const int kz = signed_freq<N>(kzi[e]);
+        const int kzi = F::out_index(tt, e);
+        const int kz = signed_freq<N>(kzi);
         const int n2 = n2xy + kz * kz;
         const bool valid = n2 > 0 && n2 < a.K2;
         const int b = valid ? isqrt_i(n2) / a.dn : 0;
-        const float iw = a.compensate >= 1 ? wxy * invw2[kzi[e]] : 1.0f;
-        const float tz = tzv[e];
+        float iw = 1.0f, noise_f = 1.0f;
+        if (a.compensate >= 1) iw = wxy * invw2[kzi];
+        if (a.compensate == 2) noise_f = cxy * alias[kzi] * iw;
+        const float2 z0 = a0[e];
+        const float q0 = (z0.x * z0.x + z0.y * z0.y) * iw;
+        double w4[4];
+        w4[0] = mu;
+        w4[1] = mu * (double)sqrtf((float)n2);
+        w4[2] = mu * (double)q0;
+        w4[3] = 0.0;
+        if (ELL >= 2) {
+          const float tz = (float)kz * twoN;
+          const float inv_t2 = 1.0f / (tx * tx + ty * ty + tz * tz);
+          const float2 A2 = acc[e];
+          w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
+        }
+        // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise
+        bin_add<4>(bins, b, valid, w4, 0);
+        double w1[1] = {mu * S * (double)noise_f};
+        bin_add<1>(bins, b, valid, w1, 5);
+      }
+    }
+    if (ELL >= 4) {
+      z_horner<N, TK, EC, 4>(base, a.h_group_stride, 4, zstride, c, t, tw, T, acc);
+      const int tt = col_hide<EC>(t);
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) {
+        const int kzi = F::out_index(tt, e);
+        const int kz = signed_freq<N>(kzi);
+        const int n2 = n2xy + kz * kz;
+        const bool valid = n2 > 0 && n2 < a.K2;
+        const int b = valid ? isqrt_i(n2) / a.dn : 0;
+        const float iw = a.compensate >= 1 ? wxy * invw2[kzi] : 1.0f;
+        const float tz = (float)kz * twoN;
         const float t2 = tx * tx + ty * ty + tz * tz;
         const float inv_t4 = 1.0f / (t2 * t2);
         const float2 z0 = a0[e];
@@ -273,16 +301,21 @@ __global__ __launch_bounds__(TK * Fft<N>::T) void zpass_kernel(const float2* __r
   for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) out[i] = bins[i];
 }
 
-template <int N, int TK, int ELL>
-static hipError_t launch_z3(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
+template <int N, int TK, int ELL, int EC>
+static hipError_t launch_z4(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
   const size_t shmem = (size_t)TK * N * sizeof(float2) + (size_t)p.nbins * kNumSums * sizeof(double);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL, EC>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((zpass_kernel<N, TK, ELL>), dim3(p.z_blocks), dim3(TK * Fft<N>::T), shmem, s,
+  hipLaunchKernelGGL((zpass_kernel<N, TK, ELL, EC>), dim3(p.z_blocks), dim3(TK * Fft<N, EC>::T), shmem, s,
                      at<const float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), at<const float>(ws, p.off_invw2),
                      at<const float>(ws, p.off_alias), at<const double>(ws, p.off_scalars),
                      at<double>(ws, p.off_zpart), a);
   return hipGetLastError();
+}
+
+template <int N, int TK, int ELL>
+static hipError_t launch_z3(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
+  return p.col_e[1] == 8 ? launch_z4<N, TK, ELL, 8>(p, ws, a, s) : launch_z4<N, TK, ELL, 16>(p, ws, a, s);
 }
 
 template <int N, int TK>

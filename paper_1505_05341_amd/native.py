@@ -44,7 +44,7 @@ class PkResult(ctypes.Structure):
 EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_result_doubles",
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
            "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
-           "pk_workspace_size_batch", "pk_multipoles_batch"]
+           "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune"]
 
 _lib = None
 
@@ -76,6 +76,10 @@ def load():
     lib.pk_workspace_size_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, P(c_size_t)]
     lib.pk_multipoles_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, c_void_p, c_size_t,
                                         P(PkResult), P(c_int32), c_void_p]
+    lib.pk_set_schedule.argtypes = [c_int32, c_int32, c_int32, c_int32]
+    lib.pk_get_schedule.argtypes = [c_int32, c_int32, P(c_int32), P(c_int32)]
+    lib.pk_autotune.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_void_p, c_size_t, c_int32, P(c_int32),
+                                P(c_int32), c_void_p]
     lib.pk_set_stage_timing.argtypes = [c_int32]
     lib.pk_stage_times.argtypes = [POINTER(c_double), c_int32]
     lib.pk_stage_times.restype = c_int32
@@ -169,3 +173,14 @@ def stage_times():
     if n < 0:
         raise RuntimeError("no timed call recorded")
     return {lib.pk_stage_name(i).decode(): float(buf[i]) for i in range(n)}
+
+
+def set_schedule(N, ell_max, y_values, z_values):
+    """Values per thread (8 or 16) of the y- and z-pass column transforms for (N, ell_max)."""
+    check(load().pk_set_schedule(int(N), int(ell_max), int(y_values), int(z_values)))
+
+
+def get_schedule(N, ell_max):
+    y, z = ctypes.c_int32(), ctypes.c_int32()
+    check(load().pk_get_schedule(int(N), int(ell_max), ctypes.byref(y), ctypes.byref(z)))
+    return int(y.value), int(z.value)

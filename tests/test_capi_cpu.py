@@ -78,3 +78,18 @@ def test_status_strings_and_result_size():
     c = native.make_config(cfg())
     import ctypes
     assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 6 + 4
+
+
+def test_schedule_table():
+    """The column-transform schedule table: defaults, round trip and rejected values."""
+    assert native.get_schedule(512, 4) == (16, 16)
+    native.set_schedule(256, 2, 8, 16)
+    try:
+        assert native.get_schedule(256, 2) == (8, 16)
+        assert native.get_schedule(256, 4) == (16, 16)   # keyed by (N, ell_max)
+    finally:
+        native.set_schedule(256, 2, 16, 16)
+    for bad in [(500, 4, 16, 16), (512, 3, 16, 16), (512, 4, 12, 16), (512, 4, 16, 4)]:
+        with pytest.raises(native.PkError) as ei:
+            native.set_schedule(*bad)
+        assert ei.value.status == -1

@@ -250,3 +250,26 @@ def test_batch_matches_single_calls_and_oracle(pk):
         if i in (0, 5):
             ref = est.pk_multipoles(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
             compare(res[i], ref, cfg)
+
+
+@pytest.mark.parametrize("N", [32, 128])
+def test_every_schedule_matches_oracle(pk, N):
+    """Both column-transform schedules of the y and z passes (16 or 8 values per thread)
+    give the oracle's multipoles; the autotuner returns one of them and keeps it."""
+    from paper_1505_05341_amd import native
+    gal, ran, cfg = catalogs.small_clustered(N=N, nbar=3e-4, ran_factor=10.0, dn=1)
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    ref = est.pk_multipoles_streamed(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
+    try:
+        for ys in (16, 8):
+            for zs in (16, 8):
+                native.set_schedule(N, cfg["ell_max"], ys, zs)
+                print("schedule", ys, zs, flush=True)
+                compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
+        best = pk.autotune(g, r, cfg, reps=2)
+        assert best[0] in (8, 16) and best[1] in (8, 16)
+        assert native.get_schedule(N, cfg["ell_max"]) == best
+        compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
+    finally:
+        native.set_schedule(N, cfg["ell_max"], 16, 16)
