@@ -91,6 +91,10 @@ typedef struct {
  *   P[(ell_max/2 + 1) * nbins]  P_0 then P_2 then P_4, bin-fastest (0 for an empty bin)
  *   noise[nbins]   shell mean of the noise subtracted from P_0, divided by I
  *   nmodes[nbins]  number of modes of the full N^3 lattice in each bin
+ *   wedges[2][nbins]  P_perp (mu in [0, 1/2]) then P_par (mu in [1/2, 1]) from the
+ *                  multipoles, the wedges of Sec. 5: P_0 -+ 3/8 P_2 +- 15/128 P_4 (the
+ *                  top-hat means of L_2 and L_4 over the two ranges); multipoles above
+ *                  ell_max are taken as 0
  * Scalars alpha, I and S (sum_g w^2 + alpha^2 sum_r w^2) are filled in. Any array
  * pointer may be NULL to skip it. On error nothing is written. */
 typedef struct {
@@ -101,6 +105,7 @@ typedef struct {
   double alpha;
   double I;
   double S;
+  double* wedges;
 } pk_result;
 
 /* Bytes of device workspace pk_multipoles needs for this configuration and these
@@ -117,7 +122,8 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
 
 /* Asynchronous form: queues the same work and leaves the results in device memory at
  * `d_result` (float64, pk_result_doubles(cfg) values: k_eff[nbins], P[(ell_max/2+1) nbins],
- * noise[nbins], nmodes[nbins] (as doubles), then alpha, I, S and the error-flag word).
+ * noise[nbins], nmodes[nbins] (as doubles), wedges[2 nbins], then alpha, I, S and the
+ * error-flag word).
  * Returns after queueing; input errors found on the device appear only in the flag word
  * (bit 1 non-finite position, 2 out of box, 4 particle at the observer, 8 non-finite
  * weight or nbar, 16 sum_r w = 0 or I <= 0). Launch-time errors are returned. */

@@ -302,6 +302,16 @@ def legendre_combination(sums, cfg: Config, I):
     return k_eff, P, noise
 
 
+def wedges(P):
+    """Sec. 5: the wedges P_perp (mu in [0, 1/2]) and P_par (mu in [1/2, 1]) from the first
+    three even multipoles, P0 -+ 3/8 P2 +- 15/128 P4 (3/8 and 15/128 are the top-hat
+    means of L_2 and L_4 over the two ranges); multipoles not measured count as zero."""
+    p0 = np.asarray(P[0], np.float64)
+    p2 = np.asarray(P[2], np.float64) if 2 in P else np.zeros_like(p0)
+    p4 = np.asarray(P[4], np.float64) if 4 in P else np.zeros_like(p0)
+    return p0 - 0.375 * p2 + (15.0 / 128.0) * p4, p0 + 0.375 * p2 - (15.0 / 128.0) * p4
+
+
 def pk_multipoles(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=None, ran_nbar=None):
     """The whole gridded Yamamoto estimator, in the paper's order (Secs. 2-4).
 

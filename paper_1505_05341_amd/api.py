@@ -57,38 +57,48 @@ class Workspace:
         return self.buf
 
 
-def _result_dict(cfg, k, P, noise, nm, res):
-    nb = cfg.nbins
-    out = {"k_eff": k, "nmodes": nm, "noise": noise, "alpha": res.alpha, "I": res.I, "S": res.S}
-    for j, ell in enumerate(range(0, cfg.ell_max + 1, 2)):
-        out["P%d" % ell] = P[j * nb:(j + 1) * nb].copy()
-    return out
+class _HostResult:
+    """Host arrays of one result and the pk_result struct that points at them."""
+
+    def __init__(self, cfg):
+        nb, nl = cfg.nbins, cfg.ell_max // 2 + 1
+        self.cfg = cfg
+        self.k, self.P, self.noise = np.zeros(nb), np.zeros(nb * nl), np.zeros(nb)
+        self.nm, self.wedges = np.zeros(nb, dtype=np.int64), np.zeros(2 * nb)
+
+    def fill(self, res):
+        dp = ctypes.POINTER(ctypes.c_double)
+        res.k_eff = self.k.ctypes.data_as(dp)
+        res.P = self.P.ctypes.data_as(dp)
+        res.noise = self.noise.ctypes.data_as(dp)
+        res.nmodes = self.nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        res.wedges = self.wedges.ctypes.data_as(dp)
+
+    def as_dict(self, res):
+        nb = self.cfg.nbins
+        out = {"k_eff": self.k, "nmodes": self.nm, "noise": self.noise, "alpha": res.alpha, "I": res.I, "S": res.S,
+               "Pperp": self.wedges[:nb].copy(), "Ppar": self.wedges[nb:].copy()}
+        for j, ell in enumerate(range(0, self.cfg.ell_max + 1, 2)):
+            out["P%d" % ell] = self.P[j * nb:(j + 1) * nb].copy()
+        return out
 
 
 def pk_multipoles(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None,
                   stream=None):
-    """Runs the estimator; returns k_eff, P0 [, P2, P4], noise, nmodes, alpha, I, S."""
+    """Runs the estimator; returns k_eff, P0 [, P2, P4], the wedges Pperp and Ppar, noise,
+    nmodes, alpha, I, S."""
     lib = native.load()
     c = native.make_config(cfg)
     cg, cr = gal.c_struct(), ran.c_struct()
     nbytes = native.workspace_size(cfg, gal.n, ran.n)
     ws = (workspace or Workspace()).get(nbytes)
-    nb = c.nbins
-    nl = c.ell_max // 2 + 1
-    k = np.zeros(nb)
-    P = np.zeros(nb * nl)
-    noise = np.zeros(nb)
-    nm = np.zeros(nb, dtype=np.int64)
+    host = _HostResult(c)
     res = native.PkResult()
-    dp = ctypes.POINTER(ctypes.c_double)
-    res.k_eff = k.ctypes.data_as(dp)
-    res.P = P.ctypes.data_as(dp)
-    res.noise = noise.ctypes.data_as(dp)
-    res.nmodes = nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    host.fill(res)
     s = stream if stream is not None else native.current_stream()
     native.check(lib.pk_multipoles(ctypes.byref(c), ctypes.byref(cg), ctypes.byref(cr),
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(res), s))
-    return _result_dict(c, k, P, noise, nm, res)
+    return host.as_dict(res)
 
 
 def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace | None = None, stream=None):
@@ -110,16 +120,9 @@ def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace |
     ws = (workspace or Workspace()).get(int(nbytes.value))
     outs = (native.PkResult * max(n, 1))()
     keep = []
-    dp = ctypes.POINTER(ctypes.c_double)
     for i in range(n):
-        c = carr[i]
-        nb, nl = c.nbins, c.ell_max // 2 + 1
-        k, P, noise, nm = np.zeros(nb), np.zeros(nb * nl), np.zeros(nb), np.zeros(nb, dtype=np.int64)
-        keep.append((k, P, noise, nm))
-        outs[i].k_eff = k.ctypes.data_as(dp)
-        outs[i].P = P.ctypes.data_as(dp)
-        outs[i].noise = noise.ctypes.data_as(dp)
-        outs[i].nmodes = nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        keep.append(_HostResult(carr[i]))
+        keep[i].fill(outs[i])
     status = (ctypes.c_int32 * max(n, 1))()
     s = stream if stream is not None else native.current_stream()
     native.check(lib.pk_multipoles_batch(carr, garr, rarr, n, lanes, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -129,8 +132,7 @@ def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace |
         if status[i] != native.PK_OK:
             results.append(None)
             continue
-        k, P, noise, nm = keep[i]
-        results.append(_result_dict(carr[i], k, P, noise, nm, outs[i]))
+        results.append(keep[i].as_dict(outs[i]))
     return results, [int(status[i]) for i in range(n)]
 
 

@@ -31,6 +31,11 @@ static int64_t isqrt64(int64_t n) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Device result layout (doubles): k_eff[nb], P[nl][nb], noise[nb], nmodes[nb],
+// wedges[2][nb], then alpha, I, S and the error flags.
+static int64_t result_size(int nb, int nl) { return (int64_t)nb * (5 + nl) + 4; }
+
+
 static bool supported_N(int N) {
   return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
 }
@@ -130,7 +135,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   }
 
   const int nl = p.ell_max / 2 + 1;
-  p.result_doubles = (int64_t)p.nbins * (3 + nl) + 4;
+  p.result_doubles = result_size(p.nbins, nl);
   const int64_t nrow = (int64_t)p.N * p.N;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -238,6 +243,24 @@ static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catal
   return PK_OK;
 }
 
+static pk_status flags_status(int flags);
+
+static pk_status unpack_result(const double* r, int nb, int nl, pk_result* o) {
+  const double* tail = r + (size_t)nb * (5 + nl);
+  const pk_status st = flags_status((int)tail[3]);
+  if (st != PK_OK) return st;
+  if (o->k_eff) memcpy(o->k_eff, r, sizeof(double) * nb);
+  if (o->P) memcpy(o->P, r + nb, sizeof(double) * nb * nl);
+  if (o->noise) memcpy(o->noise, r + (size_t)nb * (1 + nl), sizeof(double) * nb);
+  if (o->nmodes)
+    for (int b = 0; b < nb; ++b) o->nmodes[b] = (int64_t)r[(size_t)nb * (2 + nl) + b];
+  if (o->wedges) memcpy(o->wedges, r + (size_t)nb * (3 + nl), sizeof(double) * 2 * nb);
+  o->alpha = tail[0];
+  o->I = tail[1];
+  o->S = tail[2];
+  return PK_OK;
+}
+
 static pk_status flags_status(int flags) {
   if (flags & kFlagOutOfBox) return fail(PK_ERANGE, "a particle lies outside [box_min, box_min + L)");
   if (flags & kFlagNonFinitePos) return fail(PK_EDOM, "a particle position is not finite");
@@ -265,7 +288,7 @@ pk_status pk_workspace_size(const pk_config* cfg, int64_t n_gal, int64_t n_ran, 
 
 int64_t pk_result_doubles(const pk_config* cfg) {
   if (!cfg || (cfg->ell_max != 0 && cfg->ell_max != 2 && cfg->ell_max != 4) || cfg->nbins < 1) return -1;
-  return (int64_t)cfg->nbins * (3 + cfg->ell_max / 2 + 1) + 4;
+  return result_size(cfg->nbins, cfg->ell_max / 2 + 1);
 }
 
 pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
@@ -293,19 +316,7 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
   if (e != hipSuccess) return hip_fail(e, "result copy");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-  const int nb = p.nbins, nl = p.ell_max / 2 + 1;
-  const double* tail = h.data() + (size_t)nb * (3 + nl);
-  st = flags_status((int)tail[3]);
-  if (st != PK_OK) return st;
-  if (out->k_eff) memcpy(out->k_eff, h.data(), sizeof(double) * nb);
-  if (out->P) memcpy(out->P, h.data() + nb, sizeof(double) * nb * nl);
-  if (out->noise) memcpy(out->noise, h.data() + (size_t)nb * (1 + nl), sizeof(double) * nb);
-  if (out->nmodes)
-    for (int b = 0; b < nb; ++b) out->nmodes[b] = (int64_t)h[(size_t)nb * (2 + nl) + b];
-  out->alpha = tail[0];
-  out->I = tail[1];
-  out->S = tail[2];
-  return PK_OK;
+  return unpack_result(h.data(), p.nbins, p.ell_max / 2 + 1, out);
 }
 
 // ------------------------------------------------------------------- FFT schedules
@@ -537,20 +548,8 @@ pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, con
   if (e != hipSuccess) return batch_fail_cleanup(hip_fail(e, "batch results"), ls, lanes, gs, ev, 3);
   batch_fail_cleanup(PK_OK, ls, lanes, gs, ev, 3);
   for (int32_t i = 0; i < n_mocks; ++i) {
-    const int nb = cfgs[i].nbins, nl = cfgs[i].ell_max / 2 + 1;
     const double* r = h.data() + (size_t)i * rd;
-    const double* tail = r + (size_t)nb * (3 + nl);
-    per_mock[i] = flags_status((int)tail[3]);
-    if (per_mock[i] != PK_OK) continue;
-    pk_result* o = &outs[i];
-    if (o->k_eff) memcpy(o->k_eff, r, sizeof(double) * nb);
-    if (o->P) memcpy(o->P, r + nb, sizeof(double) * nb * nl);
-    if (o->noise) memcpy(o->noise, r + (size_t)nb * (1 + nl), sizeof(double) * nb);
-    if (o->nmodes)
-      for (int b = 0; b < nb; ++b) o->nmodes[b] = (int64_t)r[(size_t)nb * (2 + nl) + b];
-    o->alpha = tail[0];
-    o->I = tail[1];
-    o->S = tail[2];
+    per_mock[i] = unpack_result(r, cfgs[i].nbins, cfgs[i].ell_max / 2 + 1, &outs[i]);
   }
   return PK_OK;
 }

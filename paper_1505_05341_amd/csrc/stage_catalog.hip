@@ -626,7 +626,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
   double* P = res + nbins;
   double* noise = P + (size_t)nl * nbins;
   double* nmodes = noise + nbins;
-  double* tail = nmodes + nbins;
+  double* wedge = nmodes + nbins;  // P_perp[nbins], then P_par[nbins]
+  double* tail = wedge + 2 * nbins;
   const double cnt = red[0][0];
   if (cnt > 0.0) {
     const double den = I * cnt;
@@ -635,10 +636,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
     if (nl > 1) P[nbins + b] = 2.5 * (3.0 * red[3][0] - red[2][0]) / den;
     if (nl > 2) P[2 * nbins + b] = 1.125 * (35.0 * red[4][0] - 30.0 * red[3][0] + 3.0 * red[2][0]) / den;
     noise[b] = red[5][0] / den;
+    // wedges mu in [0, 1/2] and [1/2, 1] from the multipoles (Sec. 5): the top-hat means
+    // of L_2 and L_4 over those ranges are -+3/8 and +-15/128 (missing multipoles are 0)
+    const double p2 = nl > 1 ? P[nbins + b] : 0.0, p4 = nl > 2 ? P[2 * nbins + b] : 0.0;
+    wedge[b] = P[b] - 0.375 * p2 + (15.0 / 128.0) * p4;
+    wedge[nbins + b] = P[b] + 0.375 * p2 - (15.0 / 128.0) * p4;
   } else {
     k_eff[b] = 0.0;
     for (int l = 0; l < nl; ++l) P[l * nbins + b] = 0.0;
     noise[b] = 0.0;
+    wedge[b] = 0.0;
+    wedge[nbins + b] = 0.0;
   }
   nmodes[b] = cnt;
   if (b == 0) {

@@ -38,7 +38,8 @@ class PkConfig(ctypes.Structure):
 
 class PkResult(ctypes.Structure):
     _fields_ = [("k_eff", POINTER(c_double)), ("P", POINTER(c_double)), ("noise", POINTER(c_double)),
-                ("nmodes", POINTER(c_int64)), ("alpha", c_double), ("I", c_double), ("S", c_double)]
+                ("nmodes", POINTER(c_int64)), ("alpha", c_double), ("I", c_double), ("S", c_double),
+                ("wedges", POINTER(c_double))]
 
 
 EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_result_doubles",

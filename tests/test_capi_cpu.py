@@ -77,7 +77,8 @@ def test_status_strings_and_result_size():
     assert lib.pk_status_string(-4) == b"workspace too small"
     c = native.make_config(cfg())
     import ctypes
-    assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 6 + 4
+    # k_eff, P0 P2 P4, noise, nmodes, two wedges per bin + alpha, I, S, flags
+    assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 8 + 4
 
 
 def test_schedule_table():

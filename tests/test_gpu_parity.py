@@ -44,6 +44,9 @@ def compare(got, ref, cfg, tol=TOL):
     for ell in range(0, cfg["ell_max"] + 1, 2):
         e = np.max(np.abs(got["P%d" % ell][ok] - ref.P[ell][ok]) / raw[ok])
         errs[ell] = e
+    wperp, wpar = est.wedges(ref.P)
+    errs["perp"] = np.max(np.abs(got["Pperp"][ok] - wperp[ok]) / raw[ok])
+    errs["par"] = np.max(np.abs(got["Ppar"][ok] - wpar[ok]) / raw[ok])
     np.testing.assert_allclose(got["k_eff"][ok], ref.k_eff[ok], rtol=1e-6)
     np.testing.assert_allclose(got["noise"][ok], ref.noise[ok], rtol=1e-5)
     assert np.all(got["P0"][~ok] == 0)

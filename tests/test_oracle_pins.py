@@ -52,6 +52,38 @@ def _gold():
     return mono, counts, leg
 
 
+def _gold_wedges():
+    out = []
+    with open(GOLD) as fh:
+        for line in fh:
+            t = line.split()
+            if t and t[0] == "wedge":
+                out.append((Fraction(t[1]), Fraction(t[2]), [Fraction(v) for v in t[3:6]]))
+    return out
+
+
+def test_wedges_match_printed_coefficients_and_legendre_means():
+    """Sec. 5 wedges: the oracle's combination reproduces the printed coefficients, and
+    each coefficient is the top-hat mean of L_ell over the wedge's mu range, computed here
+    by Gauss-Legendre quadrature (exact for these polynomials)."""
+    gold = _gold_wedges()
+    assert len(gold) == 2
+    x, wq = np.polynomial.legendre.leggauss(8)
+    for side, (lo, hi, coef) in enumerate(gold):
+        for j, ell in enumerate((0, 2, 4)):
+            P = {0: np.array([0.0]), 2: np.array([0.0]), 4: np.array([0.0])}
+            P[ell] = np.array([1.0])
+            got = est.wedges(P)[side][0]
+            assert abs(got - float(coef[j])) < 1e-15
+            mu = 0.5 * (float(hi) - float(lo)) * x + 0.5 * (float(hi) + float(lo))
+            mean = 0.5 * np.sum(wq * direct.legendre(ell, mu))   # (1/(hi-lo)) * integral
+            assert abs(mean - float(coef[j])) < 1e-14, (side, ell, mean)
+    # missing multipoles count as zero
+    p0 = np.array([2.0, 3.0])
+    a, b = est.wedges({0: p0})
+    assert np.array_equal(a, p0) and np.array_equal(b, p0)
+
+
 def test_monomials_match_eqs_10_12_and_fft_counts():
     mono, counts, _ = _gold()
     for ell, n in counts.items():
