@@ -276,3 +276,66 @@ def test_every_schedule_matches_oracle(pk, N):
         compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
     finally:
         native.set_schedule(N, cfg["ell_max"], 16, 16)
+
+
+# ------------------------------------------------------------------------- degenerate inputs
+
+def _grid_catalog(pos, w, nbar):
+    return catalogs.Catalog(np.asarray(pos, np.float32), np.full(len(pos), w, np.float32),
+                            np.full(len(pos), nbar, np.float32))
+
+
+def test_particles_on_cell_edges_and_box_faces(pk):
+    """Positions exactly on grid nodes (offset 0: all CIC weight on one cell, the TSC
+    base cell rounds half up), on the lower box faces and one float32 step below the
+    upper faces (the periodic wrap)."""
+    N, L = 32, 320.0
+    box_min = (-160.0, -160.0, 400.0)
+    rng = np.random.default_rng(21)
+    H = L / N
+    nodes = np.asarray(box_min)[None, :] + rng.integers(0, N, (300, 3)) * H
+    faces = np.asarray(box_min)[None, :] + rng.random((100, 3)) * L
+    faces[:50, 0] = box_min[0]
+    faces[50:, 2] = np.nextafter(np.float32(box_min[2] + L), np.float32(-np.inf))
+    gal = _grid_catalog(np.concatenate([nodes, faces]), 1.0, 1e-4)
+    ran = catalogs.uniform_box(4000, box_min, L, 22, 1e-4)
+    for assign in (2, 3):
+        cfg = catalogs.config_dict(N, box_min, L, assign=assign)
+        got, ref = run_both(pk, gal, ran, cfg)
+        compare(got, ref, cfg)
+
+
+def test_all_galaxies_in_one_cell(pk):
+    """Extreme clustering: every galaxy in one cell, so one grid row holds them all (many
+    LDS chunks, one overloaded cell in the in-row sort), randoms uniform."""
+    N, L = 64, 600.0
+    box_min = (-300.0, -300.0, 700.0)
+    rng = np.random.default_rng(31)
+    H = L / N
+    corner = np.asarray(box_min) + np.array([17, 40, 5]) * H
+    gal = _grid_catalog(corner[None, :] + rng.random((6000, 3)) * H, 1.0, 1e-4)
+    ran = catalogs.uniform_box(20000, box_min, L, 32, 1e-4)
+    cfg = catalogs.config_dict(N, box_min, L, assign=3)
+    got, ref = run_both(pk, gal, ran, cfg)
+    compare(got, ref, cfg)
+
+
+def test_single_galaxy(pk):
+    gal, ran, cfg = catalogs.tiny_plain(n_gal=1, n_ran=5000)
+    got, ref = run_both(pk, gal, ran, cfg)
+    compare(got, ref, cfg)
+
+
+def test_empty_galaxy_catalogue_is_an_error(pk):
+    """No galaxies: alpha = 0 and I = alpha sum_r w^2 nbar = 0, so the normalisation is
+    undefined; reported as PK_EDOM."""
+    def f(c):
+        c.pos = c.pos[:0]
+        c.w = c.w[:0]
+        c.nbar = c.nbar[:0]
+    _errcase(pk, mutate_gal=f, expect=-3)
+
+
+def test_empty_batch(pk):
+    res, st = pk.pk_multipoles_batch([], [], [])
+    assert res == [] and st == []
