@@ -73,7 +73,7 @@ typedef struct {
 
 /* Estimator configuration (host memory). */
 typedef struct {
-  int32_t N;           /* grid side: 8, 16, 32, 64, 128, 256, 512 or 1024 */
+  int32_t N;           /* grid side: 8, 16, 32, 64, 128, 256, 512, 1024 or 2048 */
   int32_t assign;      /* PK_CIC or PK_TSC */
   int32_t ell_max;     /* 0, 2 or 4 -> 1, 7 or 22 LOS-weighted grids */
   int32_t los;         /* 0: each particle's own line of sight; 1: fixed +z (plane-parallel) */
@@ -84,6 +84,14 @@ typedef struct {
   double box_min[3];   /* lower corner of the periodic FFT cube */
   double L;            /* side of the cube */
   double observer[3];  /* origin of the lines of sight */
+  int32_t x_planes;    /* z planes of the x-transformed grids held at once: 0 = automatic
+                        * (all N planes while the 1, 7 or 22 x-transformed grids, 8 G N^2 Kx
+                        * bytes with Kx = nbins dn rounded up to the kx tile, take at most
+                        * 128 GiB, i.e. every N up to 1024; otherwise the largest power of two
+                        * of planes within 4 GiB), or a power of two <= N. With x_planes < N
+                        * the x and y transforms run slab by slab through that smaller buffer
+                        * (out of core: at N = 2048 the 22 grids would take 756 GB); the
+                        * result is the same to FP32 rounding. */
 } pk_config;
 
 /* Results (host memory, caller-owned arrays).
@@ -135,7 +143,8 @@ pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const
  * its own configuration). Mocks are processed in order over `lanes` (1 or 2) internal
  * HIP streams, each with its own slice of the workspace, so that one mock's short
  * kernels overlap another's transforms. Each mock's stages are captured into a hipGraph;
- * mocks of the same size class (N, assign, ell_max, nbins, dn, los, compensate) reuse
+ * mocks of the same size class (N, assign, ell_max, nbins, dn, los, compensate,
+ * norm_from and slab height) reuse
  * the instantiated graph of their lane. Work starts after everything already queued on
  * `hip_stream` and the call returns after all mocks are done.
  *   cfgs, gals, rans  arrays of n_mocks configurations and device catalogues
@@ -156,31 +165,41 @@ pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, con
 int64_t pk_result_doubles(const pk_config* cfg);
 
 /* Stage entry point for tests: runs the catalogue scalars, the row sort and the fused
- * LOS-weighted assignment with the FFT along x, then stops, leaving the x-transformed
- * grids in the workspace (same kernels as pk_multipoles). Queued on `hip_stream`. */
+ * LOS-weighted assignment with the FFT along x for the first slab of planes
+ * [0, x_planes) (all planes when the plan holds them all), then stops, leaving the
+ * x-transformed grids of that slab in the workspace (same kernels as pk_multipoles).
+ * Queued on `hip_stream`. */
 pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
                           void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Where pk_stage_xgrids leaves grid `m`: complex64 values X[z][y][kx] for kx < kx_count,
- * x-transformed (unnormalised, e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at
- * byte `offset` of the workspace. Monomial m has exponents (a, b, c) of rhat_x, rhat_y,
- * rhat_z as returned by pk_monomial. */
+/* Where pk_stage_xgrids leaves grid `m`: complex64 values X[z][y][kx] for z < x_planes
+ * (pk_x_planes), y < N, kx < kx_count: the x-transformed (unnormalised,
+ * e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at byte `offset` of the
+ * workspace. Monomial m has exponents (a, b, c) of rhat_x, rhat_y, rhat_z as returned by
+ * pk_monomial. */
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
                           size_t* offset, int32_t* kx_count);
+
+/* The slab height the plan of this configuration uses (cfg->x_planes, or the automatic
+ * choice when that is 0). PK_EINVAL / PK_ENOTSUP for an invalid configuration. */
+pk_status pk_x_planes(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t* planes);
 
 /* Schedules of the column transforms (the FFTs along y and along z): the values each
  * thread holds, 16 (radices 16, 8, 4 at N = 512: fewer threads per transform) or 8
  * (radices 8, 8, 8: half the registers). A process-wide table keyed by (N, ell_max),
  * default 16 for both passes, read when a call plans its work (not thread-safe against
  * concurrent changes). Both schedules compute the same transform; results agree to FP32
- * rounding. PK_EINVAL for an unsupported N or ell_max or values other than 8 and 16. */
+ * rounding. At N = 2048 only the 8-value schedule is built (16 values per thread would
+ * need more than 256 registers): it is the only value reported and accepted there.
+ * PK_EINVAL for an unsupported N or ell_max or values other than 8 and 16. */
 pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t z_values);
 pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t* z_values);
 
 /* Autotuner of those schedules: runs pk_multipoles once on the given inputs (same
  * arguments, workspace and errors), then times `reps` launches of every schedule of the
- * y pass and of the z pass on that data with HIP events on hip_stream, stores the
- * fastest pair in the table for (cfg->N, cfg->ell_max) and returns it. Synchronous. */
+ * y pass (on the last slab when the plan runs several) and of the z pass on that data
+ * with HIP events on hip_stream, stores the fastest pair in the table for (cfg->N,
+ * cfg->ell_max) and returns it. Synchronous. */
 pk_status pk_autotune(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
                       size_t workspace_bytes, int32_t reps, int32_t* y_values, int32_t* z_values,
                       void* hip_stream);
@@ -188,7 +207,9 @@ pk_status pk_autotune(const pk_config* cfg, const pk_catalog* gal, const pk_cata
 /* Stage timing, for measurement. While enabled (process-wide, not thread-safe), each
  * pk_multipoles / pk_multipoles_async call records HIP events on its stream around its
  * stages: 0 workspace init, 1 catalogue scalars, 2 row sort, 3 LOS assignment + x FFT,
- * 4 y FFT + z-power grouping, 5 z FFT + contraction + binning, 6 finalize.
+ * 4 y FFT + z-power grouping, 5 z FFT + contraction + binning, 6 finalize. When the
+ * plan runs several slabs (x_planes < N), stage 3 covers the x and y transforms of all
+ * slabs and stage 4 is empty.
  * pk_stage_times waits for the last call's events and writes up to n durations in
  * milliseconds; it returns the number of stages (7), or -1 if timing has no record. */
 pk_status pk_set_stage_timing(int32_t enable);

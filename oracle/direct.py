@@ -46,11 +46,12 @@ def legendre(ell, mu):
     raise ValueError(ell)
 
 
-def _axis_phase(u, N, assign):
-    """phi[p, n] = sum_c K(u_p - c) e^{-2 pi i n c / N} for n = 0..N-1 (any integer c)."""
+def _axis_phase(u, N, assign, n=None):
+    """phi[p, j] = sum_c K(u_p - c) e^{-2 pi i n_j c / N} for the frequencies n_j in
+    0..N-1 (all of them by default; any integer c)."""
     base = np.floor(u).astype(np.int64)
-    n = np.arange(N)
-    out = np.zeros((u.shape[0], N), dtype=np.complex128)
+    n = np.arange(N) if n is None else np.asarray(n, np.int64)
+    out = np.zeros((u.shape[0], len(n)), dtype=np.complex128)
     for off in range(-2, 3):
         c = base + off
         k = kernel(u - c, assign)
@@ -60,13 +61,16 @@ def _axis_phase(u, N, assign):
 
 def lattice_modes(N, dn, nbins):
     """Every full-lattice mode with 0 < |n| < nbins*dn, its bin and |n| (by explicit loops
-    over the integer components; the bin test is b*dn <= |n| < (b+1)*dn)."""
+    over the integer components, each within |n_i| < nbins*dn, which every such mode
+    satisfies; the bin test is b*dn <= |n| < (b+1)*dn)."""
     half = N // 2
     modes, bins = [], []
-    kmax2 = (nbins * dn) ** 2
-    for nx in range(-half, half):
-        for ny in range(-half, half):
-            for nz in range(-half, half):
+    kmax = nbins * dn
+    kmax2 = kmax ** 2
+    span = range(max(-half, -kmax + 1), min(half, kmax))
+    for nx in span:
+        for ny in span:
+            for nz in span:
                 q = nx * nx + ny * ny + nz * nz
                 if q == 0 or q >= kmax2:
                     continue
@@ -76,6 +80,33 @@ def lattice_modes(N, dn, nbins):
                 modes.append((nx, ny, nz))
                 bins.append(b)
     return np.array(modes, dtype=np.int64).reshape(-1, 3), np.array(bins, dtype=np.int64)
+
+
+def lattice_counts(N, dn, nbins):
+    """Number of full-lattice modes in each bin (0 < |n| < nbins*dn, components in
+    [-N/2, N/2)) without enumerating the lattice: with c1[q] the number of integers n,
+    |n| < K = nbins*dn, with n^2 = q, the number of vectors with |n|^2 = q is the
+    threefold convolution c1 * c1 * c1 at q (only q < K^2 is needed, so the component
+    range never reaches -N/2)."""
+    K = nbins * dn
+    K2 = K * K
+    c1 = np.zeros(K2, dtype=np.int64)
+    c1[0] = 1
+    j = np.arange(1, K)
+    c1[j * j] = 2
+    def conv(a):
+        out = np.zeros(K2, dtype=np.int64)
+        for v in range(K):
+            q = v * v
+            out[q:] += c1[q] * a[:K2 - q]
+        return out
+    c3 = conv(conv(c1))
+    c3[0] = 0
+    q = np.arange(K2)
+    b = np.floor(np.sqrt(q)).astype(np.int64)
+    b -= (b * b > q)
+    b += ((b + 1) * (b + 1) <= q)
+    return np.bincount(b // dn, weights=c3, minlength=nbins)[:nbins].astype(np.int64)
 
 
 def amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, funcs,
@@ -95,16 +126,18 @@ def amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, 
     else:
         d = pos - np.asarray(observer, np.float64)[None, :]
         rh = d / np.linalg.norm(d, axis=1)[:, None]
-    if method == "interp":
-        ph = [_axis_phase(u[:, i], N, assign) for i in range(3)]
     modes = np.asarray(modes, np.int64)
+    if method == "interp":
+        # the phases of the frequencies (mod N) that the modes use, one column each
+        freq = np.unique(modes % N)
+        ph = [_axis_phase(u[:, i], N, assign, freq) for i in range(3)]
     out = np.zeros((len(funcs), len(modes)), dtype=np.complex128)
     for s in range(0, len(modes), chunk):
         m = modes[s:s + chunk]
         kh = m / np.linalg.norm(m, axis=1)[:, None]
         mu = rh @ kh.T                                   # [particles, modes]
         if method == "interp":
-            idx = m % N
+            idx = np.searchsorted(freq, m % N)
             phi = ph[0][:, idx[:, 0]] * ph[1][:, idx[:, 1]] * ph[2][:, idx[:, 2]]
         else:
             phi = np.exp(-2j * np.pi * (u @ m.T.astype(np.float64)) / N)
@@ -116,12 +149,14 @@ def amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, 
 
 def direct_multipoles(gal_pos, gal_w, ran_pos, ran_w, gal_nbar, ran_nbar, *, N, box_min, L,
                       assign, observer=(0.0, 0.0, 0.0), los=0, compensate=2, dn=1, nbins=None,
-                      norm_from=0, method="interp"):
+                      norm_from=0, method="interp", chunk=512):
     """P_ell per bin from direct amplitudes with Legendre polynomials evaluated per particle:
 
       P_ell(b) = (2 ell + 1) <Re[A_0 A_{L_ell}^*] / W^2>_b / I  -  delta_{ell 0} <N>_b / I.
 
-    The catalogue scalars are recomputed here from their definitions (Sec. 2).
+    The catalogue scalars are recomputed here from their definitions (Sec. 2). Bins
+    0 .. nbins-1 are evaluated (each bin's value depends only on its own modes, so the
+    first bins of a large grid can be checked alone).
     """
     if nbins is None:
         nbins = N // (2 * dn)
@@ -138,7 +173,7 @@ def direct_multipoles(gal_pos, gal_w, ran_pos, ran_w, gal_nbar, ran_nbar, *, N, 
     modes, bins = lattice_modes(N, dn, nbins)
     ells = (0, 2, 4)
     funcs = [lambda mu, l=l: legendre(l, mu) for l in ells]
-    A = amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, funcs, method)
+    A = amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, funcs, method, chunk)
     p = assign
     x = np.pi * modes / N
     with np.errstate(invalid="ignore", divide="ignore"):
@@ -166,6 +201,8 @@ def direct_multipoles(gal_pos, gal_w, ran_pos, ran_w, gal_nbar, ran_nbar, *, N, 
         if l == 0:
             val = val - np.bincount(bins, weights=noise, minlength=nbins)[:nbins]
         out[l] = np.where(ok, val / (I * np.where(ok, cnt, 1)), 0.0)
+    out["noise"] = np.where(ok, np.bincount(bins, weights=noise, minlength=nbins)[:nbins] /
+                            (I * np.where(ok, cnt, 1)), 0.0)
     kn = np.linalg.norm(modes, axis=1)
     ks = np.bincount(bins, weights=kn, minlength=nbins)[:nbins]
     out["k_eff"] = np.where(ok, (2 * np.pi / L) * ks / np.where(ok, cnt, 1), 0.0)

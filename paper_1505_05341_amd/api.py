@@ -137,8 +137,9 @@ def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace |
 
 
 def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
-    """Runs up to the fused assignment + x transform and returns (workspace tensor, layout),
-    layout[m] = (byte offset, kx_count) of grid m (complex64 X[z][y][kx])."""
+    """Runs up to the fused assignment + x transform of the first slab of planes and
+    returns (workspace tensor, layout), layout[m] = (byte offset, kx_count, planes) of grid
+    m (complex64 X[z][y][kx] for z < planes)."""
     import torch
     lib = native.load()
     c = native.make_config(cfg)
@@ -148,21 +149,23 @@ def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: W
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), native.current_stream()))
     torch.cuda.synchronize()
     layout = {}
+    planes = native.x_planes(cfg, gal.n, ran.n)
     for m in range(native.num_grids(c.ell_max)):
         off = ctypes.c_size_t()
         kx = ctypes.c_int32()
         native.check(lib.pk_xgrid_layout(ctypes.byref(c), gal.n, ran.n, m, ctypes.byref(off), ctypes.byref(kx)))
-        layout[m] = (int(off.value), int(kx.value))
+        layout[m] = (int(off.value), int(kx.value), planes)
     return ws, layout
 
 
 def xgrid_view(ws, layout, m, N):
-    """complex64 view X[z][y][kx] of grid m inside the workspace returned by stage_xgrids."""
+    """complex64 view X[z][y][kx] (z < the slab height) of grid m inside the workspace
+    returned by stage_xgrids."""
     import torch
-    off, kx = layout[m]
-    nbytes = N * N * kx * 8
+    off, kx, planes = layout[m]
+    nbytes = planes * N * kx * 8
     raw = ws[off:off + nbytes]
-    return raw.view(torch.float32).view(N, N, kx, 2)
+    return raw.view(torch.float32).view(planes, N, kx, 2)
 
 
 def autotune(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, reps: int = 3, workspace: Workspace | None = None):

@@ -273,6 +273,62 @@ def lognormal_rsd_device(*, N_field, L, center, nbar, seed, amp=2.0e4, k0=0.1, s
     return gal, ran, tuple(float(v) for v in box_min.cpu().numpy())
 
 
+def survey_shell_device(N=2048, seed=9, N_field=512, n_gal=525000, ran_factor=10.0, L=3500.0,
+                        r_min=1200.0, r_max=1800.0, cap_deg=48.0, P_fkp=1.0e4, device="cuda", **cfg_kw):
+    """Survey-shaped stand-in for the paper's timing catalogue (one CMASS-NGC-like mock of
+    about 525,000 galaxies with randoms at 10x their density, in a cube of side 3500 Mpc/h,
+    CIC, ell = 0, 2, 4; Sec. 4 and Table 1): a lognormal RSD field (same power law, f, b as
+    the other mocks) on an N_field^3 grid, observed from the origin and cut to the shell
+    r_min <= r < r_max inside a cap of half-angle cap_deg around +z (about 2.1 sr, the
+    NGC area); nbar is set so that the shell holds about n_gal galaxies. Randoms are
+    uniform in the same shell. The cube is centred at (0, 0, 1300), so the shell and the
+    observer lie inside it. Returns (gal, ran, cfg) with device catalogues."""
+    import torch
+    from .api import DeviceCatalog
+
+    cosc = float(np.cos(np.radians(cap_deg)))
+    vol = 2.0 * np.pi * (1.0 - cosc) * (r_max ** 3 - r_min ** 3) / 3.0
+    nbar = n_gal / vol
+    center = (0.0, 0.0, 1300.0)
+    gal_all, _, box_min = lognormal_rsd_device(N_field=N_field, L=L, center=center, nbar=nbar, seed=seed,
+                                               ran_factor=0.0, P_fkp=P_fkp, device=device)
+
+    def in_shell(p):
+        p64 = p.to(torch.float64)
+        r = torch.linalg.norm(p64, dim=1)
+        return (r >= r_min) & (r < r_max) & (p64[:, 2] >= cosc * r)
+
+    keep = in_shell(gal_all.pos)
+    gpos = gal_all.pos[keep].contiguous()
+    ng = int(gpos.shape[0])
+    del gal_all
+    # randoms: uniform in the shell's bounding box, kept inside the shell
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) + 1)
+    nr = int(round(ran_factor * ng))
+    half = r_max * float(np.sqrt(1.0 - cosc * cosc))
+    lo = torch.tensor([-half, -half, r_min * cosc], dtype=torch.float64, device=device)
+    ext = torch.tensor([2 * half, 2 * half, r_max - r_min * cosc], dtype=torch.float64, device=device)
+    parts, have = [], 0
+    while have < nr:
+        q = lo[None, :] + torch.rand((max(nr - have, 1 << 20) * 3, 3), generator=gen, dtype=torch.float64,
+                                     device=device) * ext[None, :]
+        q32 = _inside_device(q, torch.tensor(box_min, dtype=torch.float64, device=device), L)
+        q32 = q32[in_shell(q32)]
+        parts.append(q32[:nr - have])
+        have += int(parts[-1].shape[0])
+    rpos = torch.cat(parts).contiguous()
+    w = float(np.float32(1.0 / (1.0 + nbar * P_fkp)))
+    f32 = torch.float32
+    gal = DeviceCatalog(gpos, torch.full((ng,), w, dtype=f32, device=device),
+                        torch.full((ng,), nbar, dtype=f32, device=device))
+    ran = DeviceCatalog(rpos, torch.full((nr,), w, dtype=f32, device=device),
+                        torch.full((nr,), nbar, dtype=f32, device=device))
+    kw = dict(assign=2, ell_max=4, dn=2)
+    kw.update(cfg_kw)
+    return gal, ran, config_dict(N, box_min, L, **kw)
+
+
 def _inside_device(pos64, box_min, L):
     """float32 positions kept in [box_min, box_min + L) when compared in float64."""
     import torch

@@ -37,7 +37,17 @@ static int64_t result_size(int nb, int nl) { return (int64_t)nb * (5 + nl) + 4; 
 
 
 static bool supported_N(int N) {
-  return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
+  return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048;
+}
+
+// Automatic slab: all planes while the whole set of x-transformed grids takes at most
+// 128 GiB (every N up to 1024), else the largest power of two of planes within 4 GiB.
+static int auto_slab(int N, int G, int Kx) {
+  const double plane = 8.0 * G * (double)N * Kx;
+  if (plane * N <= 128.0 * (1ull << 30)) return N;
+  int xs = N;
+  while (xs > 1 && plane * xs > 4.0 * (1ull << 30)) xs >>= 1;
+  return xs;
 }
 
 // Schedules of the column transforms (values per thread of the y and z passes), per
@@ -45,7 +55,7 @@ static bool supported_N(int N) {
 struct Schedule {
   int y, z;
 };
-static Schedule g_sched[11][3];
+static Schedule g_sched[12][3];
 
 static int log2_of(int N) {
   int l = 0;
@@ -74,7 +84,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.L = cfg->L;
   p.n_gal = n_gal;
   p.n_ran = n_ran;
-  if (!supported_N(p.N)) return fail(PK_ENOTSUP, "N must be one of 8, 16, 32, 64, 128, 256, 512, 1024");
+  if (!supported_N(p.N)) return fail(PK_ENOTSUP, "N must be one of 8, 16, 32, 64, 128, 256, 512, 1024, 2048");
   if (p.assign != PK_CIC && p.assign != PK_TSC) return fail(PK_EINVAL, "assign must be 2 (CIC) or 3 (TSC)");
   if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(PK_EINVAL, "ell_max must be 0, 2 or 4");
   if (p.los != 0 && p.los != 1) return fail(PK_EINVAL, "los must be 0 or 1");
@@ -87,12 +97,15 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
     if (!isfinite(p.box_min[i]) || !isfinite(p.observer[i])) return fail(PK_EINVAL, "box_min and observer must be finite");
   if (n_gal < 0 || n_ran < 0) return fail(PK_EINVAL, "catalogue sizes must be >= 0");
   if (n_gal + n_ran > (int64_t)0x7fffffff) return fail(PK_ENOTSUP, "at most 2^31 - 1 particles per call");
+  if (cfg->x_planes < 0 || cfg->x_planes > p.N || (cfg->x_planes & (cfg->x_planes - 1)) != 0)
+    return fail(PK_EINVAL, "x_planes must be 0 (automatic) or a power of two <= N");
 
   p.G = num_grids_for(p.ell_max);
   p.K = p.nbins * p.dn;
-  p.TK = p.N >= 1024 ? 8 : (p.N / 2 < 16 ? p.N / 2 : 16);   // must match tile_cols<N>() of the FFT passes
+  p.TK = p.N >= 2048 ? 4 : (p.N >= 1024 ? 8 : (p.N / 2 < 16 ? p.N / 2 : 16));  // tile_cols<N>() of the FFT passes
   p.Kx = ((p.K + p.TK - 1) / p.TK) * p.TK;
   p.nkt = p.Kx / p.TK;
+  p.xs = cfg->x_planes ? cfg->x_planes : auto_slab(p.N, p.G, p.Kx);
   // tiles: the y pass keeps |ky| <= M(kt) with kx0^2 + ky^2 < K^2, kx0 = kt * TK
   int64_t reg = 0, items = 0;
   for (int kt = 0; kt < p.nkt; ++kt) {
@@ -109,8 +122,8 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.z_items = items;
   p.z_blocks = (int)(items < 512 ? items : 512);
   const Schedule sc = g_sched[log2_of(p.N)][p.ell_max / 2];
-  p.col_e[0] = sc.y ? sc.y : 16;
-  p.col_e[1] = sc.z ? sc.z : 16;
+  p.col_e[0] = p.N >= 2048 ? 8 : (sc.y ? sc.y : 16);  // only the 8-value schedule is built at 2048
+  p.col_e[1] = p.N >= 2048 ? 8 : (sc.z ? sc.z : 16);
 
   // groups (n, c) and their members (grid index, a, b, multinomial weight)
   GroupTable& gt = p.groups;
@@ -153,11 +166,11 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_rowcnt = take(sizeof(uint32_t) * ((size_t)p.N * sort_blocks(n_gal + n_ran) + 1));  // plane histograms
   p.off_rowoff = take(sizeof(uint32_t) * (nrow + 1));
   p.off_rowhist = take(sizeof(uint32_t) * ((size_t)nrow * kRowHistParts + 1));  // per-part row counts
-  p.off_blocksum = take(sizeof(uint32_t) * 1024);
+  p.off_blocksum = take(sizeof(uint32_t) * kScanTopMax);
   p.off_tmp = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_rowkey = take(sizeof(uint16_t) * (size_t)(n_gal + n_ran));
   p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
-  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * nrow * p.Kx);
+  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * p.xs * p.N * p.Kx);  // one slab of xs planes
   p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);
   p.off_zpart = take(sizeof(double) * kNumSums * (size_t)p.z_blocks * p.nbins);
   p.off_result = take(sizeof(double) * (size_t)p.result_doubles);
@@ -228,10 +241,15 @@ static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catal
   if (timed) mark(2, s);
   if ((e = launch_sort(p, gal, ran, ws, s)) != hipSuccess) return hip_fail(e, "row sort");
   if (timed) mark(3, s);
-  if ((e = launch_xpass(p, ws, s)) != hipSuccess) return hip_fail(e, "assignment and x transform");
-  if (stop_after_x) return PK_OK;
-  if (timed) mark(4, s);
-  if ((e = launch_ypass(p, ws, s)) != hipSuccess) return hip_fail(e, "y transform");
+  // slab by slab: the y pass of a slab reads what the x pass just left in X (with one slab,
+  // xs = N, the two stages are timed apart; with several, "assign_x" covers both)
+  for (int z0 = 0; z0 < p.N; z0 += p.xs) {
+    if ((e = launch_xpass(p, ws, s, z0)) != hipSuccess) return hip_fail(e, "assignment and x transform");
+    if (stop_after_x) return PK_OK;  // X holds the first slab
+    if (timed && p.xs == p.N) mark(4, s);
+    if ((e = launch_ypass(p, ws, s, z0)) != hipSuccess) return hip_fail(e, "y transform");
+  }
+  if (timed && p.xs != p.N) mark(4, s);
   if (timed) mark(5, s);
   if ((e = launch_zpass(p, ws, s)) != hipSuccess) return hip_fail(e, "z transform and binning");
   if (timed) mark(6, s);
@@ -329,6 +347,8 @@ pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t 
   if (!schedule_key_ok(N, ell_max)) return fail(PK_EINVAL, "unsupported N or ell_max");
   if ((y_values != 8 && y_values != 16) || (z_values != 8 && z_values != 16))
     return fail(PK_EINVAL, "values per thread must be 8 or 16");
+  if (N >= 2048 && (y_values != 8 || z_values != 8))
+    return fail(PK_EINVAL, "at N = 2048 only the 8-value schedule is built");
   g_sched[log2_of(N)][ell_max / 2] = Schedule{y_values, z_values};
   return PK_OK;
 }
@@ -337,8 +357,8 @@ pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t
   if (!schedule_key_ok(N, ell_max)) return fail(PK_EINVAL, "unsupported N or ell_max");
   if (!y_values || !z_values) return fail(PK_EINVAL, "null output pointer");
   const Schedule sc = g_sched[log2_of(N)][ell_max / 2];
-  *y_values = sc.y ? sc.y : 16;
-  *z_values = sc.z ? sc.z : 16;
+  *y_values = N >= 2048 ? 8 : (sc.y ? sc.y : 16);
+  *z_values = N >= 2048 ? 8 : (sc.z ? sc.z : 16);
   return PK_OK;
 }
 
@@ -346,11 +366,13 @@ pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t
 static pk_status time_pass(Plan p, int which, int e, char* ws, int reps, hipStream_t s, hipEvent_t a, hipEvent_t b,
                            float* ms) {
   p.col_e[which] = e;
-  hipError_t err = which == 0 ? launch_ypass(p, ws, s) : launch_zpass(p, ws, s);  // warm-up
+  // the y pass is timed on the last slab, whose x-transformed rows X still holds
+  const int z0 = p.N - p.xs;
+  hipError_t err = which == 0 ? launch_ypass(p, ws, s, z0) : launch_zpass(p, ws, s);  // warm-up
   if (err != hipSuccess) return hip_fail(err, "autotune warm-up");
   if ((err = hipEventRecord(a, s)) != hipSuccess) return hip_fail(err, "event record");
   for (int r = 0; r < reps; ++r) {
-    err = which == 0 ? launch_ypass(p, ws, s) : launch_zpass(p, ws, s);
+    err = which == 0 ? launch_ypass(p, ws, s, z0) : launch_zpass(p, ws, s);
     if (err != hipSuccess) return hip_fail(err, "autotune launch");
   }
   if ((err = hipEventRecord(b, s)) != hipSuccess) return hip_fail(err, "event record");
@@ -381,13 +403,14 @@ pk_status pk_autotune(const pk_config* cfg, const pk_catalog* gal, const pk_cata
     return hip_fail(err, "event create");
   }
   const int cand[2] = {16, 8};
-  int best[2] = {16, 16};
+  const int k0 = p.N >= 2048 ? 1 : 0;  // 8 only at 2048
+  int best[2] = {cand[k0], cand[k0]};
   for (int which = 0; which < 2 && st == PK_OK; ++which) {
     float tbest = 0.0f;
-    for (int k = 0; k < 2 && st == PK_OK; ++k) {
+    for (int k = k0; k < 2 && st == PK_OK; ++k) {
       float ms = 0.0f;
       st = time_pass(p, which, cand[k], static_cast<char*>(workspace), reps, s, a, b, &ms);
-      if (st == PK_OK && (k == 0 || ms < tbest)) {
+      if (st == PK_OK && (k == k0 || ms < tbest)) {
         tbest = ms;
         best[which] = cand[k];
       }
@@ -429,13 +452,13 @@ static pk_status batch_layout(const pk_config* cfgs, const pk_catalog* gals, con
 
 struct GraphSlot {
   bool valid = false;
-  int key[8] = {0};
+  int key[9] = {0};
   hipGraphExec_t exec = nullptr;
 };
 
-static void class_key(const Plan& p, int (&k)[8]) {
+static void class_key(const Plan& p, int (&k)[9]) {
   k[0] = p.N; k[1] = p.assign; k[2] = p.ell_max; k[3] = p.nbins; k[4] = p.dn; k[5] = p.los; k[6] = p.compensate;
-  k[7] = p.norm_from;
+  k[7] = p.norm_from; k[8] = p.xs;
 }
 
 }  // extern "C"
@@ -510,7 +533,7 @@ pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, con
       g_timing.enabled = timing;
       return batch_fail_cleanup(st != PK_OK ? st : hip_fail(e, "end capture"), ls, lanes, gs, ev, 3);
     }
-    int key[8];
+    int key[9];
     class_key(p, key);
     bool reused = false;
     if (gs[l].valid && memcmp(gs[l].key, key, sizeof(key)) == 0) {
@@ -570,8 +593,18 @@ pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, in
   if (st != PK_OK) return st;
   if (m < 0 || m >= p.G) return fail(PK_EINVAL, "grid index out of range");
   if (!offset || !kx_count) return fail(PK_EINVAL, "null output pointer");
-  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.N * p.N * p.Kx;
+  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.xs * p.N * p.Kx;
   *kx_count = p.Kx;
+  return PK_OK;
+}
+
+pk_status pk_x_planes(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t* planes) {
+  if (!planes) return fail(PK_EINVAL, "null output pointer");
+  Plan p;
+  const char* why;
+  pk_status st = make_plan(cfg, n_gal, n_ran, &p, &why);
+  if (st != PK_OK) return st;
+  *planes = p.xs;
   return PK_OK;
 }
 

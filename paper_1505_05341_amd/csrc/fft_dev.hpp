@@ -1,5 +1,5 @@
 // Device building blocks of the batched FFTs: complex helpers, in-register DFTs of
-// size <= 16 and a multi-stage Stockham transform of length N <= 1024 along one axis.
+// size <= 16 and a multi-stage Stockham transform of length N <= 2048 along one axis.
 //
 // Stockham (self-sorting) formulation: with radices R_0, R_1, ... (product N) and
 // Ns = R_0 ... R_{s-1} before stage s, butterfly j (0 <= j < N/R_s) of stage s reads
@@ -78,6 +78,7 @@ template <> struct Radices<128, 16>  { static constexpr int NS = 2, R0 = 16, R1 
 template <> struct Radices<256, 16>  { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 1, R3 = 1; };
 template <> struct Radices<512, 16>  { static constexpr int NS = 3, R0 = 16, R1 = 8,  R2 = 4, R3 = 1; };
 template <> struct Radices<1024, 16> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4, R3 = 1; };
+template <> struct Radices<2048, 16> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 8, R3 = 1; };
 template <> struct Radices<8, 8>     { static constexpr int NS = 2, R0 = 4,  R1 = 2,  R2 = 1, R3 = 1; };
 template <> struct Radices<16, 8>    { static constexpr int NS = 2, R0 = 4,  R1 = 4,  R2 = 1, R3 = 1; };
 template <> struct Radices<32, 8>    { static constexpr int NS = 2, R0 = 8,  R1 = 4,  R2 = 1, R3 = 1; };
@@ -86,6 +87,7 @@ template <> struct Radices<128, 8>   { static constexpr int NS = 3, R0 = 8,  R1 
 template <> struct Radices<256, 8>   { static constexpr int NS = 3, R0 = 8,  R1 = 8,  R2 = 4, R3 = 1; };
 template <> struct Radices<512, 8>   { static constexpr int NS = 3, R0 = 8,  R1 = 8,  R2 = 8, R3 = 1; };
 template <> struct Radices<1024, 8>  { static constexpr int NS = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 2; };
+template <> struct Radices<2048, 8>  { static constexpr int NS = 4, R0 = 8,  R1 = 8,  R2 = 8, R3 = 4; };
 
 template <int N, int EMAX = 16>
 struct Fft {

@@ -12,9 +12,10 @@ namespace pk {
 constexpr int kMaxGrids = 22;
 constexpr int kMaxGroups = 9;
 constexpr int kMaxMembers = 5;
-constexpr int kMaxTiles = 64;       // kx tiles of 16 columns up to N = 2048
+constexpr int kMaxTiles = 256;      // kx tiles: 16 columns up to N = 512, 8 at 1024, 4 at 2048
 constexpr int kStatsBlocks = 2048;  // blocks of the catalogue-scalar reduction
 constexpr int kScanChunk = 4096;    // counters per scan block
+constexpr int kScanTopMax = 4096;   // scan blocks of one scan (N^2 kRowHistParts / kScanChunk at N = 2048)
 constexpr int kSortBlocks = 2048;   // level-A sort blocks (one contiguous particle range each)
 constexpr int kRowHistParts = 4;    // level-B blocks per plane
 constexpr int kNumSums = 6;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise
@@ -81,7 +82,7 @@ struct Plan {
   int TK;         // kx columns per FFT tile
   int Kx;         // kx columns kept after the x transform (multiple of TK, <= N/2)
   int nkt;        // kx tiles
-  int x_split;    // blocks per x row (grids split between them)
+  int xs;         // z planes of the x-transformed grids held at once (the slab; divides N)
   int z_blocks;   // persistent blocks of the z pass
   int col_e[2];   // values per thread of the column transforms of the y and z passes (8 or 16)
   int64_t z_items;
@@ -102,8 +103,10 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
 hipError_t launch_init(const Plan& p, char* ws, hipStream_t s);  // also copies the group and tile tables
 hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s);
 hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s);
-hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s);
-hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s);
+// The x and y passes work on the slab of planes [z0, z0 + xs): the x pass writes the
+// slab's x-transformed rows into X (which holds xs planes), the y pass reads them there.
+hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0);
+hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0);
 hipError_t launch_zpass(const Plan& p, char* ws, hipStream_t s);
 hipError_t launch_finalize(const Plan& p, char* ws, double* d_result, hipStream_t s);
 

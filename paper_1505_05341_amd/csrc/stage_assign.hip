@@ -30,7 +30,8 @@ struct XArgs {
   float obs[3];
   int los;
   int Kx;
-  int64_t grid_stride;  // float2 elements per grid of X: N * N * Kx
+  int z0;               // first plane of the slab
+  int64_t grid_stride;  // float2 elements per grid of X: xs * N * Kx (xs planes per slab)
 };
 
 __host__ __device__ constexpr int num_grids(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
@@ -49,9 +50,8 @@ __device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&
   m[17] = yy * yy; m[18] = yy * yz; m[19] = yy * zz; m[20] = yz * zz; m[21] = zz * zz;
 }
 
-// Block geometry: 512 threads and chunks of 1024 particles up to N = 512; at N = 1024 one
-// block of 1024 threads (one cell per thread, all 22 grids in one block, so the particle
-// work is done once per target row) and chunks of 2048.
+// Block geometry: 512 threads and chunks of 1024 particles up to N = 512; from N = 1024 on,
+// blocks of 1024 threads (one cell per thread at 1024, two at 2048) and chunks of 2048.
 template <int N>
 struct XGeom {
   static constexpr int NT = N >= 1024 ? 1024 : 512;      // threads
@@ -104,6 +104,15 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
   if (tid == NT - 1) st[N] = ex;
   __syncthreads();
 }
+
+// Blocks per target row: the 22 rows of 2048 cells (176 KB) exceed the LDS, so at
+// N = 2048 two blocks share a row, 11 grids each (each does the particle work).
+template <int N, int ELL>
+constexpr int xpass_split() { return (N >= 2048 && ELL == 4) ? 2 : 1; }
+
+// One-visit gather (see gather_rows) at N = 1024, where it pays for its S x registers.
+template <int N>
+constexpr bool xpass_one_visit() { return N == 1024; }
 
 // Gathers rows G0 .. G0+NG of the block's target row into LDS rows[g - G0][x]
 // (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
@@ -277,7 +286,7 @@ struct XSwizzle {
 };
 
 // Waves per SIMD the registers are budgeted for: 6 (3 blocks of 512 threads per CU, as
-// the LDS allows; <= 80 VGPRs) up to N = 512, 4 (one block of 1024 threads) at 1024.
+// the LDS allows; <= 80 VGPRs) up to N = 512, 4 (one block of 1024 threads) from 1024 on.
 template <int N>
 constexpr int xpass_waves() { return N >= 1024 ? 4 : 6; }
 
@@ -294,12 +303,12 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
-  // the rows of planes [j N/8, (j+1) N/8) in order and the source rows that neighbouring
-  // target rows share stay in that XCD's L2.
+  // the rows of the slab's planes [j xs/8, (j+1) xs/8) in order (xs = gridDim.y) and the
+  // source rows that neighbouring target rows share stay in that XCD's L2.
   const int part = blockIdx.z;
   const uint32_t lin = blockIdx.x + blockIdx.y * (uint32_t)N;
-  const uint32_t logical = (lin & 7u) * (uint32_t)(N * N / 8) + (lin >> 3);
-  const int y = (int)(logical % N), z = (int)(logical / N);
+  const uint32_t logical = (lin & 7u) * (uint32_t)(N * gridDim.y / 8) + (lin >> 3);
+  const int y = (int)(logical % N), zs = (int)(logical / N), z = a.z0 + zs;
   const int g0 = part * GB;
   const int ng = G - g0 < GB ? G - g0 : GB;
 
@@ -312,14 +321,16 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     const int sy = (y - oy) & (N - 1), sz = (z - oz) & (N - 1);
     const int64_t r = (int64_t)sz * N + sy;
     beg[s] = rowoff[r];
-    pre[s + 1] = pre[s] + (rowoff[r + 1] - beg[s]);
+    const uint32_t end = rowoff[r + 1];
+    pre[s + 1] = pre[s] + (end > beg[s] ? end - beg[s] : 0u);  // offsets are non-decreasing
   }
+  constexpr bool OV = xpass_one_visit<N>();
   if (SPLIT == 1) {
-    gather_rows<N, ASSIGN, G, 0, G, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, 0, G, NP, OV>(lds, sorted, beg, pre, a);
   } else if (part == 0) {
-    gather_rows<N, ASSIGN, G, 0, GB, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, 0, GB, NP, OV>(lds, sorted, beg, pre, a);
   } else {
-    gather_rows<N, ASSIGN, G, GB, G - GB, NP, (N >= 1024)>(lds, sorted, beg, pre, a);
+    gather_rows<N, ASSIGN, G, GB, G - GB, NP, OV>(lds, sorted, beg, pre, a);
   }
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
@@ -347,7 +358,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   __syncthreads();
   // X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = -i (Z[k] - conj Z[N-k]) / 2
   const int Kx = a.Kx;
-  const size_t row = ((size_t)z * N + y) * (size_t)Kx;
+  const size_t row = ((size_t)zs * N + y) * (size_t)Kx;
   for (int e = tid; e < npairs * Kx; e += blockDim.x) {
     const int qq = e / Kx, kx = e - qq * Kx;
     const float2 zk = T[qq * N + XSwizzle()(kx)];
@@ -362,14 +373,14 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
 template <int N, int ASSIGN, int ELL>
 static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
   constexpr int G = num_grids(ELL);
-  constexpr int SPLIT = 1;
+  constexpr int SPLIT = xpass_split<N, ELL>();
   constexpr int GB = (G + SPLIT - 1) / SPLIT;
   constexpr int NP = (GB + 1) / 2;
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
   const size_t shmem = rows > gather_lds_bytes<N>() ? rows : gather_lds_bytes<N>();
   hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL, SPLIT>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, N, SPLIT), dim3(XGeom<N>::NT), shmem, s,
+  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, p.xs, SPLIT), dim3(XGeom<N>::NT), shmem, s,
                      at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
                      at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);
   return hipGetLastError();
@@ -389,7 +400,7 @@ static hipError_t launch_x1(const Plan& p, char* ws, const XArgs& a, hipStream_t
   return p.assign == PK_CIC ? launch_x2<N, PK_CIC>(p, ws, a, s) : launch_x2<N, PK_TSC>(p, ws, a, s);
 }
 
-hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s) {
+hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0) {
   XArgs a;
   for (int i = 0; i < 3; ++i) {
     a.bmin[i] = (float)p.box_min[i];
@@ -398,7 +409,8 @@ hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s) {
   a.invH = (float)((double)p.N / p.L);
   a.los = p.los;
   a.Kx = p.Kx;
-  a.grid_stride = (int64_t)p.N * p.N * p.Kx;
+  a.z0 = z0;
+  a.grid_stride = (int64_t)p.xs * p.N * p.Kx;
   switch (p.N) {
     case 8: return launch_x1<8>(p, ws, a, s);
     case 16: return launch_x1<16>(p, ws, a, s);
@@ -408,6 +420,7 @@ hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s) {
     case 256: return launch_x1<256>(p, ws, a, s);
     case 512: return launch_x1<512>(p, ws, a, s);
     case 1024: return launch_x1<1024>(p, ws, a, s);
+    case 2048: return launch_x1<2048>(p, ws, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -35,22 +35,30 @@ __global__ __launch_bounds__(256) void init_kernel(int N, int assign, int* flags
   }
 }
 
-// Copies the group and tile tables (passed by value as 32-bit words) into the workspace.
-struct TableWords {
-  uint32_t w[(sizeof(GroupTable) + sizeof(TileTable) + 3) / 4];
+// Copies the group and tile tables into the workspace, passed by value as 32-bit words
+// in pieces of at most 2 KB of kernel arguments (so that a captured graph holds them).
+constexpr int kTableChunkWords = 512;
+constexpr int kTableWords = (int)((sizeof(GroupTable) + sizeof(TileTable) + 3) / 4);
+struct TableChunk {
+  uint32_t w[kTableChunkWords];
 };
 
-__global__ __launch_bounds__(256) void copy_tables_kernel(const TableWords tw, uint32_t* out) {
-  constexpr int n = sizeof(TableWords) / 4;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = tw.w[i];
+__global__ __launch_bounds__(256) void copy_tables_kernel(const TableChunk c, int n, uint32_t* out) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = c.w[i];
 }
 
 hipError_t launch_init(const Plan& p, char* ws, hipStream_t s) {
-  TableWords words;
-  memset(&words, 0, sizeof(words));
-  memcpy(&words, &p.groups, sizeof(GroupTable));
-  memcpy(reinterpret_cast<char*>(&words) + sizeof(GroupTable), &p.tiles, sizeof(TileTable));
-  hipLaunchKernelGGL(copy_tables_kernel, dim3(1), dim3(256), 0, s, words, at<uint32_t>(ws, p.off_tables));
+  uint32_t words[kTableWords];
+  memset(words, 0, sizeof(words));
+  memcpy(words, &p.groups, sizeof(GroupTable));
+  memcpy(reinterpret_cast<char*>(words) + sizeof(GroupTable), &p.tiles, sizeof(TileTable));
+  for (int w0 = 0; w0 < kTableWords; w0 += kTableChunkWords) {
+    const int n = kTableWords - w0 < kTableChunkWords ? kTableWords - w0 : kTableChunkWords;
+    TableChunk c;
+    memset(&c, 0, sizeof(c));
+    memcpy(c.w, words + w0, sizeof(uint32_t) * n);
+    hipLaunchKernelGGL(copy_tables_kernel, dim3(1), dim3(256), 0, s, c, n, at<uint32_t>(ws, p.off_tables) + w0);
+  }
   const int blocks = (p.N + 255) / 256;
   hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, p.N, p.assign, at<int>(ws, p.off_flags),
                      at<float2>(ws, p.off_tw), at<float>(ws, p.off_invw2), at<float>(ws, p.off_alias));
@@ -484,12 +492,21 @@ __global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* cnt, i
   if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
 }
 
-// Exclusive scan of up to 1024 block sums in one block.
+// Exclusive scan of up to kScanTopMax block sums in one block of 1024 threads, four
+// consecutive sums per thread.
 __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* blocksum, int nb) {
+  constexpr int PER = kScanTopMax / 1024;
   __shared__ uint32_t a[1024];
   const int t = threadIdx.x;
-  const uint32_t v = t < nb ? blocksum[t] : 0u;
-  a[t] = v;
+  uint32_t v[PER];
+  uint32_t loc = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = t * PER + j;
+    v[j] = i < nb ? blocksum[i] : 0u;
+    loc += v[j];
+  }
+  a[t] = loc;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
     const uint32_t add = t >= off ? a[t - off] : 0u;
@@ -497,7 +514,13 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* blocksum, int 
     a[t] += add;
     __syncthreads();
   }
-  if (t < nb) blocksum[t] = a[t] - v;
+  uint32_t run = a[t] - loc;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = t * PER + j;
+    if (i < nb) blocksum[i] = run;
+    run += v[j];
+  }
 }
 
 // Exclusive scan, second level: out[i] = offset of element i (in place allowed), out[n] = total.
@@ -565,13 +588,22 @@ hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& r
     hipLaunchKernelGGL(plane_hist_kernel<PK_TSC>, dim3(B), dim3(256), shA, s, gal, ran, g, per, ph, at<int>(ws, p.off_flags));
   const int64_t nph = (int64_t)p.N * B;
   const int nb = (int)((nph + kScanChunk - 1) / kScanChunk);
+  const int64_t nrh = (int64_t)p.N * p.N * kRowParts;
+  const int nbr = (int)((nrh + kScanChunk - 1) / kScanChunk);
+  if (nb > kScanTopMax || nbr > kScanTopMax) return hipErrorInvalidValue;  // the block-sum buffer
   uint32_t* bsum = at<uint32_t>(ws, p.off_blocksum);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, ph, nph, bsum);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
   hipLaunchKernelGGL(scan_down_kernel, dim3(nb), dim3(256), 0, s, ph, nph, bsum, ph);
   float4* tmp = at<float4>(ws, p.off_tmp);
   uint16_t* rowkey = at<uint16_t>(ws, p.off_rowkey);
-  const size_t shS = staged_lds_bytes(p.N);
+  const size_t shS = staged_lds_bytes(p.N);  // above 64 KB at N = 2048
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&plane_scatter_kernel<PK_CIC>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shS);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&plane_scatter_kernel<PK_TSC>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shS);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&row_sort_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shS);
   if (p.assign == PK_CIC)
     hipLaunchKernelGGL(plane_scatter_kernel<PK_CIC>, dim3(B), dim3(kSortThreads), shS, s, gal, ran, g, per, ph,
                        at<const double>(ws, p.off_scalars), tmp, rowkey);
@@ -581,8 +613,6 @@ hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& r
   uint32_t* rh = at<uint32_t>(ws, p.off_rowhist);
   hipLaunchKernelGGL(row_hist_kernel, dim3(kRowParts, p.N), dim3(kSortThreads), sizeof(uint32_t) * p.N, s, rowkey, ph,
                      B, p.N, rh);
-  const int64_t nrh = (int64_t)p.N * p.N * kRowParts;
-  const int nbr = (int)((nrh + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nbr), dim3(256), 0, s, rh, nrh, bsum);
   hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, bsum, nbr);
   hipLaunchKernelGGL(scan_down_kernel, dim3(nbr), dim3(256), 0, s, rh, nrh, bsum, rh);

@@ -25,7 +25,8 @@ namespace pk {
 
 struct YArgs {
   int Kx;
-  int64_t x_grid_stride;
+  int z0;                 // first plane of the slab held in X
+  int64_t x_grid_stride;  // xs N Kx
   int64_t h_group_stride;
   const GroupTable* gt;   // device copies (dynamic indexing of by-value kernel
   const TileTable* tt;    // arguments would push them to scratch)
@@ -46,9 +47,18 @@ struct ColSlot {
 };
 
 // kx columns per tile: 16 (128-byte rows) up to N = 512; 8 at N = 1024, where a
-// 16-column tile would need 1024-thread blocks and their 128-register cap.
+// 16-column tile would need 1024-thread blocks and their 128-register cap; 4 at 2048,
+// where the 8-value schedule needs 256 threads per column.
 template <int N>
-constexpr int tile_cols() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }
+constexpr int tile_cols() { return N >= 2048 ? 4 : (N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16)); }
+
+// Linear block id -> logical id such that blocks with consecutive logical ids run on one
+// XCD (workgroups go to the 8 XCDs round-robin): tiles narrower than a 128-byte line
+// share lines with their neighbours, which then meet in that XCD's L2. Needs a multiple
+// of 8 blocks; otherwise the identity.
+__device__ __forceinline__ uint32_t xcd_group(uint32_t lin, uint32_t nblk) {
+  return (nblk & 7u) ? lin : (lin & 7u) * (nblk >> 3) + (lin >> 3);
+}
 
 // Column transforms come in two schedules, picked per plan (the autotuner times both):
 // EC = 16 values per thread (radices 16, 8, 4 at 512: fewer threads) or EC = 8 (radices
@@ -68,7 +78,9 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
   using F = Fft<N, EC>;
   extern __shared__ float2 T[];
   const int tid0 = threadIdx.x;
-  const int kt = blockIdx.x, z = blockIdx.y;
+  const uint32_t nblk = gridDim.x * gridDim.y;
+  const uint32_t lb = xcd_group(blockIdx.x + blockIdx.y * gridDim.x, nblk);
+  const int kt = (int)(lb % gridDim.x), zs = (int)(lb / gridDim.x), z = a.z0 + zs;
   const GroupTable& gt = *a.gt;
   const int M = a.tt->M[kt];
   const int64_t regoff = a.tt->regoff[kt];
@@ -91,7 +103,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
       const int c = tid % TK, t = tid / TK;
       const int kx = kt * TK + c;
       const int m = gt.grid[g][s];
-      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)z * N * Kx + kx;
+      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)zs * N * Kx + kx;
       float2 d[F::E];
 #pragma unroll
       for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * Kx];
@@ -115,23 +127,24 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
 }
 
 template <int N, int TK>
-static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s) {
+static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0) {
   YArgs a;
   a.Kx = p.Kx;
-  a.x_grid_stride = (int64_t)p.N * p.N * p.Kx;
+  a.z0 = z0;
+  a.x_grid_stride = (int64_t)p.xs * p.N * p.Kx;
   a.h_group_stride = (int64_t)p.H_group_stride;
   a.gt = at<const GroupTable>(ws, p.off_tables);
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
   const size_t shmem = (size_t)TK * N * sizeof(float2);
-  if (p.col_e[0] == 8) {
+  if (N >= 2048 || p.col_e[0] == 8) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 8>), dim3(p.nkt, N), dim3(TK * Fft<N, 8>::T), shmem, s,
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 8>), dim3(p.nkt, p.xs), dim3(TK * Fft<N, 8>::T), shmem, s,
                        at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
-  } else {
+  } else if constexpr (N < 2048) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 16>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 16>), dim3(p.nkt, N), dim3(TK * Fft<N, 16>::T), shmem, s,
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 16>), dim3(p.nkt, p.xs), dim3(TK * Fft<N, 16>::T), shmem, s,
                        at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
   }
   return hipGetLastError();
@@ -223,9 +236,15 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
   for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) bins[i] = 0.0;
   const double S = scal[kNoiseS];
   const float twoN = 2.0f / N;
-  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
-    int kt = 0;
-    for (int k = 1; k < a.nkt; ++k) kt = item >= a.tt->item0[k] ? k : kt;
+  // consecutive items (neighbouring ky columns of one tile, which share lines when the
+  // tile is narrower than 128 bytes) go to blocks of one XCD
+  const int64_t first = xcd_group(blockIdx.x, gridDim.x);
+  for (int64_t item = first; item < a.n_items; item += gridDim.x) {
+    int kt = 0, hi = a.nkt;  // the tile: the last kt with item0[kt] <= item
+    while (hi - kt > 1) {
+      const int mid = (kt + hi) >> 1;
+      if (a.tt->item0[mid] <= item) kt = mid; else hi = mid;
+    }
     const int M = a.tt->M[kt];
     const int s = (int)(item - a.tt->item0[kt]);
     const int ky = s - M;
@@ -313,9 +332,15 @@ static hipError_t launch_z4(const Plan& p, char* ws, const ZArgs& a, hipStream_t
   return hipGetLastError();
 }
 
+// At N = 2048 only the 8-value schedule is built: with 16 values per thread the column
+// transforms need more than 256 registers.
 template <int N, int TK, int ELL>
 static hipError_t launch_z3(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
-  return p.col_e[1] == 8 ? launch_z4<N, TK, ELL, 8>(p, ws, a, s) : launch_z4<N, TK, ELL, 16>(p, ws, a, s);
+  if constexpr (N >= 2048) {
+    return launch_z4<N, TK, ELL, 8>(p, ws, a, s);
+  } else {
+    return p.col_e[1] == 8 ? launch_z4<N, TK, ELL, 8>(p, ws, a, s) : launch_z4<N, TK, ELL, 16>(p, ws, a, s);
+  }
 }
 
 template <int N, int TK>
@@ -339,16 +364,17 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
 
 
 
-hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s) {
+hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0) {
   switch (p.N) {
-    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s);
-    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s);
-    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s);
-    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s);
-    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s);
-    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s);
-    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s);
-    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s);
+    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s, z0);
+    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s, z0);
+    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s, z0);
+    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s, z0);
+    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s, z0);
+    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s, z0);
+    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s, z0);
+    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s, z0);
+    case 2048: return launch_y2<2048, tile_cols<2048>()>(p, ws, s, z0);
     default: return hipErrorInvalidValue;
   }
 }
@@ -363,6 +389,7 @@ hipError_t launch_zpass(const Plan& p, char* ws, hipStream_t s) {
     case 256: return launch_z2<256, tile_cols<256>()>(p, ws, s);
     case 512: return launch_z2<512, tile_cols<512>()>(p, ws, s);
     case 1024: return launch_z2<1024, tile_cols<1024>()>(p, ws, s);
+    case 2048: return launch_z2<2048, tile_cols<2048>()>(p, ws, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -33,7 +33,7 @@ class PkCatalog(ctypes.Structure):
 class PkConfig(ctypes.Structure):
     _fields_ = [("N", c_int32), ("assign", c_int32), ("ell_max", c_int32), ("los", c_int32),
                 ("compensate", c_int32), ("dn", c_int32), ("nbins", c_int32), ("norm_from", c_int32),
-                ("box_min", c_double * 3), ("L", c_double), ("observer", c_double * 3)]
+                ("box_min", c_double * 3), ("L", c_double), ("observer", c_double * 3), ("x_planes", c_int32)]
 
 
 class PkResult(ctypes.Structure):
@@ -45,7 +45,8 @@ class PkResult(ctypes.Structure):
 EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_result_doubles",
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
            "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
-           "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune"]
+           "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune",
+           "pk_x_planes"]
 
 _lib = None
 
@@ -67,6 +68,7 @@ def load():
     lib.pk_result_doubles.restype = c_int64
     lib.pk_stage_xgrids.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_void_p, c_size_t, c_void_p]
     lib.pk_xgrid_layout.argtypes = [P(PkConfig), c_int64, c_int64, c_int32, P(c_size_t), P(c_int32)]
+    lib.pk_x_planes.argtypes = [P(PkConfig), c_int64, c_int64, P(c_int32)]
     lib.pk_num_grids.argtypes = [c_int32]
     lib.pk_num_grids.restype = c_int32
     lib.pk_monomial.argtypes = [c_int32, P(c_int32), P(c_int32), P(c_int32)]
@@ -120,6 +122,7 @@ def make_config(cfg: dict) -> PkConfig:
         c.box_min[i] = cfg["box_min"][i]
         c.observer[i] = cfg.get("observer", (0.0, 0.0, 0.0))[i]
     c.L = cfg["L"]
+    c.x_planes = cfg.get("x_planes", 0)
     return c
 
 
@@ -144,6 +147,13 @@ def workspace_size(cfg: dict, n_gal: int, n_ran: int) -> int:
     lib = load()
     out = c_size_t(0)
     check(lib.pk_workspace_size(ctypes.byref(make_config(cfg)), n_gal, n_ran, ctypes.byref(out)))
+    return int(out.value)
+
+
+def x_planes(cfg: dict, n_gal: int, n_ran: int) -> int:
+    """Slab height (z planes of the x-transformed grids held at once) of this plan."""
+    out = c_int32(0)
+    check(load().pk_x_planes(ctypes.byref(make_config(cfg)), n_gal, n_ran, ctypes.byref(out)))
     return int(out.value)
 
 

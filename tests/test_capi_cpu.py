@@ -48,9 +48,10 @@ def test_workspace_size_grows_with_particles_and_grid():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(N=48), -6), (dict(N=2048, nbins=8), -6), (dict(ell_max=3), -1), (dict(assign=1), -1),
+    (dict(N=48), -6), (dict(N=4096, nbins=8), -6), (dict(ell_max=3), -1), (dict(assign=1), -1),
     (dict(los=2), -1), (dict(compensate=3), -1), (dict(dn=0), -1), (dict(nbins=33), -1),
     (dict(nbins=0), -1), (dict(L=-1.0), -1), (dict(norm_from=2), -1),
+    (dict(x_planes=3), -1), (dict(x_planes=128), -1), (dict(x_planes=-2), -1),
 ])
 def test_bad_configurations(kw, code):
     c = native.make_config(cfg(**kw))
@@ -81,6 +82,26 @@ def test_status_strings_and_result_size():
     assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 8 + 4
 
 
+def test_slab_plans():
+    """Slab height of the x-transformed grids: all planes up to N = 1024 (the whole set fits
+    in 128 GiB), out of core at 2048 (22 grids would take 756 GB), and the workspace shrinks
+    by exactly the planes not held."""
+    assert native.x_planes(cfg(), 10, 100) == 64
+    assert native.x_planes(cfg(N=1024, nbins=256, dn=2), 10, 100) == 1024
+    c2048 = cfg(N=2048, nbins=512, dn=2, L=3500.0)
+    # one plane of the 22 grids: 22 * 2048 rows * 1024 kx * 8 bytes; 8 planes fit in 4 GiB
+    assert native.x_planes(c2048, 525000, 5250000) == 8
+    assert native.x_planes(dict(c2048, ell_max=0), 10, 100) == 2048   # 1 grid: 34 GB
+    total = native.workspace_size(c2048, 525000, 5250000)
+    assert total < 280 * 2 ** 30, total / 2 ** 30
+    full = native.workspace_size(cfg(), 10, 100)
+    for xs in (1, 8, 32):
+        small = native.workspace_size(cfg(x_planes=xs), 10, 100)
+        assert native.x_planes(cfg(x_planes=xs), 10, 100) == xs
+        # Kx = nbins * dn = 32 columns at N = 64
+        assert full - small == 22 * (64 - xs) * 64 * 32 * 8
+
+
 def test_schedule_table():
     """The column-transform schedule table: defaults, round trip and rejected values."""
     assert native.get_schedule(512, 4) == (16, 16)
@@ -90,7 +111,9 @@ def test_schedule_table():
         assert native.get_schedule(256, 4) == (16, 16)   # keyed by (N, ell_max)
     finally:
         native.set_schedule(256, 2, 16, 16)
-    for bad in [(500, 4, 16, 16), (512, 3, 16, 16), (512, 4, 12, 16), (512, 4, 16, 4)]:
+    assert native.get_schedule(2048, 4) == (8, 8)   # the only schedule built at 2048
+    native.set_schedule(2048, 4, 8, 8)
+    for bad in [(500, 4, 16, 16), (512, 3, 16, 16), (512, 4, 12, 16), (512, 4, 16, 4), (2048, 4, 16, 8)]:
         with pytest.raises(native.PkError) as ei:
             native.set_schedule(*bad)
         assert ei.value.status == -1

@@ -24,12 +24,17 @@ def pk():
     return pk
 
 
+def oracle_config(cfg):
+    """The estimator's configuration (x_planes only sets how the GPU schedules its work)."""
+    return est.Config(**{k: v for k, v in cfg.items() if k != "x_planes"})
+
+
 def run_both(pk, gal, ran, cfg):
     print("case", {k: v for k, v in cfg.items() if k not in ("box_min", "observer")}, gal.n, ran.n, flush=True)
     g = pk.DeviceCatalog.from_host(gal)
     r = pk.DeviceCatalog.from_host(ran)
     got = pk.pk_multipoles(g, r, cfg)
-    ref = est.pk_multipoles_streamed(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
+    ref = est.pk_multipoles_streamed(gal.pos, gal.w, ran.pos, ran.w, oracle_config(cfg), gal.nbar, ran.nbar)
     return got, ref
 
 
@@ -276,6 +281,52 @@ def test_every_schedule_matches_oracle(pk, N):
         compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
     finally:
         native.set_schedule(N, cfg["ell_max"], 16, 16)
+
+
+@pytest.mark.parametrize("N,assign,xs", [(32, 2, 1), (32, 3, 4), (64, 3, 8), (64, 2, 32)])
+def test_slabs_match_oracle(pk, N, assign, xs):
+    """Out of core: the x and y transforms run slab by slab through a buffer of xs planes
+    (as at N = 2048). The multipoles are the oracle's; the buffer holds the oracle's
+    x-transformed rows of the first slab (z < xs, with the rows whose TSC stencil wraps to
+    the top plane); a batch mixing slabbed and whole plans and the autotuner agree too."""
+    from paper_1505_05341_amd import native
+    gal, ran, cfg = catalogs.small_clustered(N=N, nbar=3e-4, ran_factor=10.0, assign=assign, dn=1)
+    scfg = dict(cfg, x_planes=xs)
+    assert native.x_planes(scfg, gal.n, ran.n) == xs
+    got, ref = run_both(pk, gal, ran, scfg)
+    compare(got, ref, cfg)
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    ws, layout = pk.stage_xgrids(g, r, scfg)
+    assert layout[0][2] == xs
+    c = oracle_config(cfg)
+    alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    wp = est.signed_weights(gal.w, ran.w, alpha)
+    rng = np.random.default_rng(N + xs)
+    for m in (0, 6, 21):
+        X = pk.xgrid_view(ws, layout, m, N).cpu().numpy()
+        assert X.shape[0] == xs
+        mono = native.monomial(m)
+        for iz in sorted({0, xs - 1}):
+            iy = int(rng.integers(0, N))
+            ref_row = est.x_transformed_row(pos, wp, c, mono, iy, iz)
+            kx = layout[m][1]
+            gotrow = X[iz, iy, :, 0] + 1j * X[iz, iy, :, 1]
+            scale = np.sqrt(np.mean(np.abs(ref_row[:kx]) ** 2)) + 1e-30
+            assert np.max(np.abs(gotrow - ref_row[:kx])) / scale < 1e-5, (m, iy, iz)
+    del ws
+    res, st = pk.pk_multipoles_batch([g, g, g], [r, r, r], [scfg, cfg, scfg], lanes=2)
+    assert st == [0, 0, 0]
+    for out in res:
+        compare(out, ref, cfg)
+    if xs == 4:
+        try:
+            best = pk.autotune(g, r, scfg, reps=1)
+            assert best[0] in (8, 16) and best[1] in (8, 16)
+            compare(pk.pk_multipoles(g, r, scfg), ref, cfg)
+        finally:
+            native.set_schedule(N, cfg["ell_max"], 16, 16)
 
 
 # ------------------------------------------------------------------------- degenerate inputs

@@ -309,6 +309,18 @@ def test_mode_counts_against_lattice_loops():
         [0, 1, 1, 2, 3, 4, 4, 999999, 1000000]
 
 
+def test_lattice_counts_by_convolution():
+    """The bin counts by convolving 1-D square counts (used where the lattice is too large
+    to enumerate) equal the enumeration, and their total is the number of lattice points
+    in the ball, within the known O(K^1.5) lattice-point error of its volume."""
+    for N, dn, nb in [(8, 1, 4), (16, 1, 8), (32, 3, 5), (32, 2, 8), (64, 1, 20)]:
+        _, bins = direct.lattice_modes(N, dn, nb)
+        np.testing.assert_array_equal(direct.lattice_counts(N, dn, nb), np.bincount(bins, minlength=nb))
+    K = 512
+    tot = int(direct.lattice_counts(1024, 1, K).sum()) + 1   # + the origin
+    assert abs(tot - 4.0 / 3.0 * np.pi * K ** 3) < 4 * K ** 1.5
+
+
 def test_weight_and_density_scalings():
     gal, ran, cfg = _small_case(N=8)
     r0 = _run(gal, ran, cfg)
