@@ -131,7 +131,7 @@ def cpu_baseline(gal, ran, cfg):
     22 x (assignment + FFT). The contraction and binning are left out (the real oracle is
     slower still)."""
     from oracle import estimator as est
-    c = est.Config(**cfg)
+    c = est.Config(**{k: v for k, v in cfg.items() if k != "x_planes"})
     t0 = time.perf_counter()
     alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar, c.norm_from)
     pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--workload", default="clustered_512",
                     help="clustered_512 (default), desi_1024, survey (with --grid), tiny_32, batch, correction")
     ap.add_argument("--grid", type=int, default=2048, help="grid of --workload survey (512, 1024 or 2048)")
+    ap.add_argument("--x-planes", type=int, default=0,
+                    help="planes per slab of the x and y transforms (0 = the library's automatic choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mocks", type=int, default=256, help="ensemble size for --workload batch")
     ap.add_argument("--lanes", type=int, default=2, help="concurrent lanes for --workload batch")
@@ -320,6 +322,8 @@ def main():
     log("generating workload", args.workload)
     t = time.perf_counter()
     gal, ran, cfg, desc = make_workload(args.workload, args.grid)
+    if args.x_planes:
+        cfg = dict(cfg, x_planes=args.x_planes)
     log("generated %d galaxies + %d randoms in %.1f s" % (gal.n, ran.n, time.perf_counter() - t))
     torch.cuda.set_device(0)
     torch.cuda.synchronize()

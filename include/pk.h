@@ -84,14 +84,17 @@ typedef struct {
   double box_min[3];   /* lower corner of the periodic FFT cube */
   double L;            /* side of the cube */
   double observer[3];  /* origin of the lines of sight */
-  int32_t x_planes;    /* z planes of the x-transformed grids held at once: 0 = automatic
-                        * (all N planes while the 1, 7 or 22 x-transformed grids, 8 G N^2 Kx
-                        * bytes with Kx = nbins dn rounded up to the kx tile, take at most
-                        * 128 GiB, i.e. every N up to 1024; otherwise the largest power of two
-                        * of planes within 4 GiB), or a power of two <= N. With x_planes < N
-                        * the x and y transforms run slab by slab through that smaller buffer
-                        * (out of core: at N = 2048 the 22 grids would take 756 GB); the
-                        * result is the same to FP32 rounding. */
+  int32_t x_planes;    /* z planes per slab of the x and y transforms: 0 = automatic (all
+                        * N planes while the 1, 7 or 22 x-transformed grids, 8 G N^2 Kx bytes
+                        * with Kx = nbins dn rounded up to the kx tile, take at most 128 GiB,
+                        * i.e. every N up to 1024; otherwise the largest power of two of
+                        * planes whose two slabs fit in 8 GiB), or a power of two <= N. With
+                        * x_planes < N the transforms run slab by slab and the x-transformed
+                        * grids are held for two slabs only (out of core: at N = 2048 the 22
+                        * grids would take 756 GB); the y transform of one slab runs on a
+                        * second stream of the library while the x transform of the next runs
+                        * on the caller's stream (not while the stream is being captured into
+                        * a graph). The result is the same to FP32 rounding. */
 } pk_config;
 
 /* Results (host memory, caller-owned arrays).

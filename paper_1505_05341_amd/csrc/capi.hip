@@ -40,13 +40,13 @@ static bool supported_N(int N) {
   return N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024 || N == 2048;
 }
 
-// Automatic slab: all planes while the whole set of x-transformed grids takes at most
-// 128 GiB (every N up to 1024), else the largest power of two of planes within 4 GiB.
+// Automatic slab: all planes while the x-transformed grids take at most 128 GiB (every N
+// up to 1024), else the largest power of two of planes whose two slots fit in 8 GiB.
 static int auto_slab(int N, int G, int Kx) {
+  if (8.0 * G * (double)N * Kx * N <= 128.0 * (1ull << 30)) return N;
   const double plane = 8.0 * G * (double)N * Kx;
-  if (plane * N <= 128.0 * (1ull << 30)) return N;
   int xs = N;
-  while (xs > 1 && plane * xs > 4.0 * (1ull << 30)) xs >>= 1;
+  while (xs > 1 && 2.0 * plane * xs > 8.0 * (1ull << 30)) xs >>= 1;
   return xs;
 }
 
@@ -106,6 +106,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.Kx = ((p.K + p.TK - 1) / p.TK) * p.TK;
   p.nkt = p.Kx / p.TK;
   p.xs = cfg->x_planes ? cfg->x_planes : auto_slab(p.N, p.G, p.Kx);
+  p.xr = p.N / p.xs < 2 ? 1 : 2;  // X holds two slabs (double buffer) when there are several
   // tiles: the y pass keeps |ky| <= M(kt) with kx0^2 + ky^2 < K^2, kx0 = kt * TK
   int64_t reg = 0, items = 0;
   for (int kt = 0; kt < p.nkt; ++kt) {
@@ -170,7 +171,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_tmp = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_rowkey = take(sizeof(uint16_t) * (size_t)(n_gal + n_ran));
   p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
-  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * p.xs * p.N * p.Kx);  // one slab of xs planes
+  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * p.xr * p.xs * p.N * p.Kx);  // xr slots of xs planes
   p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);
   p.off_zpart = take(sizeof(double) * kNumSums * (size_t)p.z_blocks * p.nbins);
   p.off_result = take(sizeof(double) * (size_t)p.result_doubles);
@@ -220,6 +221,76 @@ static void mark(int i, hipStream_t s) {
   if (g_timing.enabled && g_timing.ev[i]) hipEventRecord(g_timing.ev[i], s);
 }
 
+// Second stream of the calling thread on each device, on which the y pass of slab i runs
+// while the x pass of slab i + 1 runs on the caller's stream (the x pass is bound by
+// arithmetic, the y pass by memory). Default priority, non-blocking; events order the
+// two: y(i) after x(i), and with two slots x(i) after y(i - 2).
+constexpr int kMaxDevices = 16;
+constexpr int kPipeEvents = 64;
+struct Pipe {
+  bool ready = false;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, ex[kPipeEvents] = {}, ey[kPipeEvents] = {};
+};
+static thread_local Pipe g_pipe[kMaxDevices];
+
+static hipError_t pipe_for_device(Pipe** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  Pipe& pp = g_pipe[dev];
+  if (!pp.ready) {
+    if ((e = hipStreamCreateWithFlags(&pp.aux, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&pp.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    for (int i = 0; i < kPipeEvents; ++i) {
+      if ((e = hipEventCreateWithFlags(&pp.ex[i], hipEventDisableTiming)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&pp.ey[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    pp.ready = true;
+  }
+  *out = &pp;
+  return hipSuccess;
+}
+
+// The x and y passes over every slab. Slab i covers planes [i xs, (i + 1) xs) and uses
+// slot i mod xr of X. With one slab, or while `s` is being captured into a graph, both
+// passes run in order on `s`; otherwise the y passes run on the second stream, each after
+// its slab's x pass (an event on `s`), and an x pass that reuses a slot waits for the y
+// pass that read it; `s` finally waits for the last y pass.
+static hipError_t run_slabs(const Plan& p, char* ws, hipStream_t s, bool stop_after_x, bool timed) {
+  const int nslab = p.N / p.xs;
+  hipError_t e;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
+  Pipe* pp = nullptr;
+  if (nslab > 1 && !stop_after_x && cs == hipStreamCaptureStatusNone && p.xr <= kPipeEvents) {
+    if ((e = pipe_for_device(&pp)) != hipSuccess) return e;
+  }
+  if (!pp) {
+    for (int i = 0; i < nslab; ++i) {
+      const int z0 = i * p.xs, pb = (i % p.xr) * p.xs;
+      if ((e = launch_xpass(p, ws, s, z0, pb)) != hipSuccess) return e;
+      if (stop_after_x) return hipSuccess;  // X holds the first slab
+      if (timed && nslab == 1) mark(4, s);
+      if ((e = launch_ypass(p, ws, s, z0, pb)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if ((e = hipEventRecord(pp->fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(pp->aux, pp->fork, 0)) != hipSuccess) return e;
+  for (int i = 0; i < nslab; ++i) {
+    const int z0 = i * p.xs, pb = (i % p.xr) * p.xs;
+    if (i >= p.xr && (e = hipStreamWaitEvent(s, pp->ey[(i - p.xr) % kPipeEvents], 0)) != hipSuccess) return e;
+    if ((e = launch_xpass(p, ws, s, z0, pb)) != hipSuccess) return e;
+    if ((e = hipEventRecord(pp->ex[i % kPipeEvents], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(pp->aux, pp->ex[i % kPipeEvents], 0)) != hipSuccess) return e;
+    if ((e = launch_ypass(p, ws, pp->aux, z0, pb)) != hipSuccess) return e;
+    if ((e = hipEventRecord(pp->ey[i % kPipeEvents], pp->aux)) != hipSuccess) return e;
+  }
+  return hipStreamWaitEvent(s, pp->ey[(nslab - 1) % kPipeEvents], 0);
+}
+
 static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, double* d_result,
                             hipStream_t s, bool stop_after_x) {
   hipError_t e;
@@ -241,14 +312,10 @@ static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catal
   if (timed) mark(2, s);
   if ((e = launch_sort(p, gal, ran, ws, s)) != hipSuccess) return hip_fail(e, "row sort");
   if (timed) mark(3, s);
-  // slab by slab: the y pass of a slab reads what the x pass just left in X (with one slab,
-  // xs = N, the two stages are timed apart; with several, "assign_x" covers both)
-  for (int z0 = 0; z0 < p.N; z0 += p.xs) {
-    if ((e = launch_xpass(p, ws, s, z0)) != hipSuccess) return hip_fail(e, "assignment and x transform");
-    if (stop_after_x) return PK_OK;  // X holds the first slab
-    if (timed && p.xs == p.N) mark(4, s);
-    if ((e = launch_ypass(p, ws, s, z0)) != hipSuccess) return hip_fail(e, "y transform");
-  }
+  // with one slab (xs = N) the x and y stages are timed apart; with several, "assign_x"
+  // covers both
+  if ((e = run_slabs(p, ws, s, stop_after_x, timed)) != hipSuccess) return hip_fail(e, "x and y transforms");
+  if (stop_after_x) return PK_OK;
   if (timed && p.xs != p.N) mark(4, s);
   if (timed) mark(5, s);
   if ((e = launch_zpass(p, ws, s)) != hipSuccess) return hip_fail(e, "z transform and binning");
@@ -367,12 +434,12 @@ static pk_status time_pass(Plan p, int which, int e, char* ws, int reps, hipStre
                            float* ms) {
   p.col_e[which] = e;
   // the y pass is timed on the last slab, whose x-transformed rows X still holds
-  const int z0 = p.N - p.xs;
-  hipError_t err = which == 0 ? launch_ypass(p, ws, s, z0) : launch_zpass(p, ws, s);  // warm-up
+  const int z0 = p.N - p.xs, pb = ((p.N / p.xs - 1) % p.xr) * p.xs;
+  hipError_t err = which == 0 ? launch_ypass(p, ws, s, z0, pb) : launch_zpass(p, ws, s);  // warm-up
   if (err != hipSuccess) return hip_fail(err, "autotune warm-up");
   if ((err = hipEventRecord(a, s)) != hipSuccess) return hip_fail(err, "event record");
   for (int r = 0; r < reps; ++r) {
-    err = which == 0 ? launch_ypass(p, ws, s, z0) : launch_zpass(p, ws, s);
+    err = which == 0 ? launch_ypass(p, ws, s, z0, pb) : launch_zpass(p, ws, s);
     if (err != hipSuccess) return hip_fail(err, "autotune launch");
   }
   if ((err = hipEventRecord(b, s)) != hipSuccess) return hip_fail(err, "event record");
@@ -593,7 +660,7 @@ pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, in
   if (st != PK_OK) return st;
   if (m < 0 || m >= p.G) return fail(PK_EINVAL, "grid index out of range");
   if (!offset || !kx_count) return fail(PK_EINVAL, "null output pointer");
-  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.xs * p.N * p.Kx;
+  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.xr * p.xs * p.N * p.Kx;
   *kx_count = p.Kx;
   return PK_OK;
 }

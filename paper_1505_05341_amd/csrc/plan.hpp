@@ -82,7 +82,8 @@ struct Plan {
   int TK;         // kx columns per FFT tile
   int Kx;         // kx columns kept after the x transform (multiple of TK, <= N/2)
   int nkt;        // kx tiles
-  int xs;         // z planes of the x-transformed grids held at once (the slab; divides N)
+  int xs;         // z planes per slab of the x and y passes (divides N)
+  int xr;         // slabs X holds: 1 (xs = N) or 2 (slab i uses slot i % 2)
   int z_blocks;   // persistent blocks of the z pass
   int col_e[2];   // values per thread of the column transforms of the y and z passes (8 or 16)
   int64_t z_items;
@@ -104,9 +105,10 @@ hipError_t launch_init(const Plan& p, char* ws, hipStream_t s);  // also copies 
 hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s);
 hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, hipStream_t s);
 // The x and y passes work on the slab of planes [z0, z0 + xs): the x pass writes the
-// slab's x-transformed rows into X (which holds xs planes), the y pass reads them there.
-hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0);
-hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0);
+// slab's x-transformed rows into planes [pbase, pbase + xs) of X (which holds xr xs
+// planes), the y pass reads them there.
+hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase);
+hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase);
 hipError_t launch_zpass(const Plan& p, char* ws, hipStream_t s);
 hipError_t launch_finalize(const Plan& p, char* ws, double* d_result, hipStream_t s);
 

@@ -31,7 +31,8 @@ struct XArgs {
   int los;
   int Kx;
   int z0;               // first plane of the slab
-  int64_t grid_stride;  // float2 elements per grid of X: xs * N * Kx (xs planes per slab)
+  int pbase;            // plane of X that receives plane z0
+  int64_t grid_stride;  // float2 elements per grid of X: xr * xs * N * Kx
 };
 
 __host__ __device__ constexpr int num_grids(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   __syncthreads();
   // X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = -i (Z[k] - conj Z[N-k]) / 2
   const int Kx = a.Kx;
-  const size_t row = ((size_t)zs * N + y) * (size_t)Kx;
+  const size_t row = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx;
   for (int e = tid; e < npairs * Kx; e += blockDim.x) {
     const int qq = e / Kx, kx = e - qq * Kx;
     const float2 zk = T[qq * N + XSwizzle()(kx)];
@@ -400,7 +401,7 @@ static hipError_t launch_x1(const Plan& p, char* ws, const XArgs& a, hipStream_t
   return p.assign == PK_CIC ? launch_x2<N, PK_CIC>(p, ws, a, s) : launch_x2<N, PK_TSC>(p, ws, a, s);
 }
 
-hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0) {
+hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   XArgs a;
   for (int i = 0; i < 3; ++i) {
     a.bmin[i] = (float)p.box_min[i];
@@ -410,7 +411,8 @@ hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0) {
   a.los = p.los;
   a.Kx = p.Kx;
   a.z0 = z0;
-  a.grid_stride = (int64_t)p.xs * p.N * p.Kx;
+  a.pbase = pbase;
+  a.grid_stride = (int64_t)p.xr * p.xs * p.N * p.Kx;
   switch (p.N) {
     case 8: return launch_x1<8>(p, ws, a, s);
     case 16: return launch_x1<16>(p, ws, a, s);

@@ -25,8 +25,9 @@ namespace pk {
 
 struct YArgs {
   int Kx;
-  int z0;                 // first plane of the slab held in X
-  int64_t x_grid_stride;  // xs N Kx
+  int z0;                 // first plane of the slab
+  int pbase;              // plane of X that holds plane z0
+  int64_t x_grid_stride;  // xr xs N Kx
   int64_t h_group_stride;
   const GroupTable* gt;   // device copies (dynamic indexing of by-value kernel
   const TileTable* tt;    // arguments would push them to scratch)
@@ -103,7 +104,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
       const int c = tid % TK, t = tid / TK;
       const int kx = kt * TK + c;
       const int m = gt.grid[g][s];
-      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)zs * N * Kx + kx;
+      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * Kx + kx;
       float2 d[F::E];
 #pragma unroll
       for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * Kx];
@@ -127,11 +128,12 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
 }
 
 template <int N, int TK>
-static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0) {
+static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   YArgs a;
   a.Kx = p.Kx;
   a.z0 = z0;
-  a.x_grid_stride = (int64_t)p.xs * p.N * p.Kx;
+  a.pbase = pbase;
+  a.x_grid_stride = (int64_t)p.xr * p.xs * p.N * p.Kx;
   a.h_group_stride = (int64_t)p.H_group_stride;
   a.gt = at<const GroupTable>(ws, p.off_tables);
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
@@ -364,17 +366,17 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
 
 
 
-hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0) {
+hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   switch (p.N) {
-    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s, z0);
-    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s, z0);
-    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s, z0);
-    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s, z0);
-    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s, z0);
-    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s, z0);
-    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s, z0);
-    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s, z0);
-    case 2048: return launch_y2<2048, tile_cols<2048>()>(p, ws, s, z0);
+    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s, z0, pbase);
+    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s, z0, pbase);
+    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s, z0, pbase);
+    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s, z0, pbase);
+    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s, z0, pbase);
+    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s, z0, pbase);
+    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s, z0, pbase);
+    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s, z0, pbase);
+    case 2048: return launch_y2<2048, tile_cols<2048>()>(p, ws, s, z0, pbase);
     default: return hipErrorInvalidValue;
   }
 }
