@@ -1,14 +1,17 @@
 // LOS-weighted mass assignment fused with the FFT along x (Sec. 3, Eqs. 11 and 13;
 // Sec. 4 for the assignment).
 //
-// One block owns one target grid row (y, z) for a group of the 1, 7 or 22 monomial
-// grids F rhat^m. The particles whose stencil reaches the row are those of a few
-// source rows, which the counting sort made contiguous. They are processed in chunks:
+// One block owns one target grid row (y, z) of the 1, 7 or 22 monomial grids F rhat^m.
+// Only the 1, 6 or 15 monomials with a power of rhat_z below 2 are gathered and
+// transformed; the others follow exactly from rhat_x^2 + rhat_y^2 + rhat_z^2 = 1 and are
+// written as combinations of the transformed rows (basis.hpp). The particles whose
+// stencil reaches the row are those of a few source rows, which the counting sort made
+// contiguous. They are processed in chunks:
 //   1. each particle's own line of sight rhat = (x - observer)/|x - observer|, its
 //      base cell along x, its x offset and its weight w' W_y W_z go to LDS;
 //   2. the chunk is counting-sorted by base cell in LDS (integer atomics only);
 //   3. each thread owns target cells and gathers, from the particles of the 2 (CIC)
-//      or 3 (TSC) source cells that reach it, w' W rhat^m for every grid of the block,
+//      or 3 (TSC) source cells that reach it, w' W rhat^m for every gathered monomial,
 //      summing in registers.
 // No floating-point atomics are used: on gfx950 LDS float atomics run several times
 // slower than integer ones, and a scatter would need one per particle, cell and grid.
@@ -18,6 +21,7 @@
 // binned sphere).
 #include <hip/hip_runtime.h>
 
+#include "basis.hpp"
 #include "fft_dev.hpp"
 #include "particle.hpp"
 #include "plan.hpp"
@@ -37,18 +41,19 @@ struct XArgs {
 
 __host__ __device__ constexpr int num_grids(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
 
-// Monomials rhat^m in the fixed order (degree 0; degree 2: xx xy xz yy yz zz;
-// degree 4: each as the product of two degree-2 values).
-template <int G>
-__device__ __forceinline__ void monomials(float rx, float ry, float rz, float (&m)[G]) {
+// The gathered monomials rhat^m (power of rhat_z at most 1) in kept order (basis.hpp):
+// 1; xx xy xz yy yz; xx.xx xx.xy xx.xz xx.yy xx.yz xy.yy xy.yz yy.yy yy.yz.
+template <int GK>
+__device__ __forceinline__ void kept_monomials(float rx, float ry, float rz, float (&m)[GK]) {
   m[0] = 1.0f;
-  if (G == 1) return;
-  const float xx = rx * rx, xy = rx * ry, xz = rx * rz, yy = ry * ry, yz = ry * rz, zz = rz * rz;
-  m[1] = xx; m[2] = xy; m[3] = xz; m[4] = yy; m[5] = yz; m[6] = zz;
-  if (G == 7) return;
-  m[7] = xx * xx;  m[8] = xx * xy;  m[9] = xx * xz;  m[10] = xx * yy; m[11] = xx * yz;
-  m[12] = xx * zz; m[13] = xy * yy; m[14] = xy * yz; m[15] = xy * zz; m[16] = xz * zz;
-  m[17] = yy * yy; m[18] = yy * yz; m[19] = yy * zz; m[20] = yz * zz; m[21] = zz * zz;
+  if constexpr (GK > 1) {
+    const float xx = rx * rx, xy = rx * ry, xz = rx * rz, yy = ry * ry, yz = ry * rz;
+    m[1] = xx; m[2] = xy; m[3] = xz; m[4] = yy; m[5] = yz;
+    if constexpr (GK > 6) {
+      m[6] = xx * xx;  m[7] = xx * xy;  m[8] = xx * xz;  m[9] = xx * yy;  m[10] = xx * yz;
+      m[11] = xy * yy; m[12] = xy * yz; m[13] = yy * yy; m[14] = yy * yz;
+    }
+  }
 }
 
 // Block geometry: 512 threads and chunks of 1024 particles up to N = 512; from N = 1024 on,
@@ -106,18 +111,13 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
   __syncthreads();
 }
 
-// Blocks per target row: the 22 rows of 2048 cells (176 KB) exceed the LDS, so at
-// N = 2048 two blocks share a row, 11 grids each (each does the particle work).
-template <int N, int ELL>
-constexpr int xpass_split() { return (N >= 2048 && ELL == 4) ? 2 : 1; }
-
 // One-visit gather (see gather_rows) at N = 1024, where it pays for its S x registers.
 template <int N>
 constexpr bool xpass_one_visit() { return N == 1024; }
 
-// Gathers rows G0 .. G0+NG of the block's target row into LDS rows[g - G0][x]
+// Gathers the NG kept monomial rows of the block's target row into LDS rows[g][x]
 // (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
-template <int N, int ASSIGN, int G, int G0, int NG, int NP, bool OV, int S = (ASSIGN == PK_CIC ? 2 : 3)>
+template <int N, int ASSIGN, int NG, int NP, bool OV, int S = (ASSIGN == PK_CIC ? 2 : 3)>
 __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict__ sorted, const uint32_t (&beg)[S * S],
                                             const uint32_t (&pre)[S * S + 1], const XArgs& a) {
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
@@ -218,12 +218,12 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
             float wo[S];
 #pragma unroll
             for (int o = 0; o < S; ++o) wo[o] = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
-            float m[G];
-            monomials<G>(p.z, p.w, pr[i], m);
+            float m[NG];
+            kept_monomials<NG>(p.z, p.w, pr[i], m);
 #pragma unroll
             for (int g = 0; g < NG; ++g)
 #pragma unroll
-              for (int o = 0; o < NS; ++o) acc[c][o][g] += wo[o] * m[G0 + g];
+              for (int o = 0; o < NS; ++o) acc[c][o][g] += wo[o] * m[g];
           }
         } else {
           // target cell x receives from base cells x - O0 - o with stencil offset O0 + o
@@ -235,10 +235,10 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
               const int i = perm[k];
               const float4 p = pa[i];
               const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
-              float m[G];
-              monomials<G>(p.z, p.w, pr[i], m);
+              float m[NG];
+              kept_monomials<NG>(p.z, p.w, pr[i], m);
 #pragma unroll
-              for (int g = 0; g < NG; ++g) acc[c][0][g] += w * m[G0 + g];
+              for (int g = 0; g < NG; ++g) acc[c][0][g] += w * m[g];
             }
           }
         }
@@ -286,17 +286,29 @@ struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
 
-// Waves per SIMD the registers are budgeted for: 6 (3 blocks of 512 threads per CU, as
-// the LDS allows; <= 80 VGPRs) up to N = 512, 4 (one block of 1024 threads) from 1024 on.
+// Waves per SIMD the registers are budgeted for: 8 (4 blocks of 512 threads per CU, which
+// the 32 KB of LDS of the 15 gathered rows allow; <= 64 VGPRs, measured 11% faster than 6)
+// up to N = 512, 4 (one block of 1024 threads) from 1024 on.
 template <int N>
-constexpr int xpass_waves() { return N >= 1024 ? 4 : 6; }
+constexpr int xpass_waves() { return N >= 1024 ? 4 : 8; }
 
-template <int N, int ASSIGN, int ELL, int SPLIT>
+// x-transformed value at kx of kept row j, from the packed spectra in LDS: rows (2q, 2q+1)
+// were transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
+// X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
+template <int N>
+__device__ __forceinline__ float2 kept_spectrum(const float2* T, int j, int kx) {
+  const float2 zk = T[(j >> 1) * N + XSwizzle()(kx)];
+  const float2 zm = T[(j >> 1) * N + XSwizzle()((N - kx) & (N - 1))];
+  return (j & 1) ? make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x))
+                 : make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+}
+
+template <int N, int ASSIGN, int ELL>
 __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
-  constexpr int G = num_grids(ELL);
-  constexpr int GB = (G + SPLIT - 1) / SPLIT;
-  constexpr int NP = (GB + 1) / 2;
+  constexpr int GK = kept_count(ELL);   // gathered and transformed rows
+  constexpr int ND = dep_count(ELL);    // rows written as their combinations
+  constexpr int NP = (GK + 1) / 2;
   constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
   using F = Fft<N>;
@@ -306,12 +318,9 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
   // the rows of the slab's planes [j xs/8, (j+1) xs/8) in order (xs = gridDim.y) and the
   // source rows that neighbouring target rows share stay in that XCD's L2.
-  const int part = blockIdx.z;
   const uint32_t lin = blockIdx.x + blockIdx.y * (uint32_t)N;
   const uint32_t logical = (lin & 7u) * (uint32_t)(N * gridDim.y / 8) + (lin >> 3);
   const int y = (int)(logical % N), zs = (int)(logical / N), z = a.z0 + zs;
-  const int g0 = part * GB;
-  const int ng = G - g0 < GB ? G - g0 : GB;
 
   // source rows: the particles whose base cell (iy, iz) = (y - oy, z - oz) reach this row
   uint32_t beg[S * S], pre[S * S + 1];
@@ -325,19 +334,11 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     const uint32_t end = rowoff[r + 1];
     pre[s + 1] = pre[s] + (end > beg[s] ? end - beg[s] : 0u);  // offsets are non-decreasing
   }
-  constexpr bool OV = xpass_one_visit<N>();
-  if (SPLIT == 1) {
-    gather_rows<N, ASSIGN, G, 0, G, NP, OV>(lds, sorted, beg, pre, a);
-  } else if (part == 0) {
-    gather_rows<N, ASSIGN, G, 0, GB, NP, OV>(lds, sorted, beg, pre, a);
-  } else {
-    gather_rows<N, ASSIGN, G, GB, G - GB, NP, OV>(lds, sorted, beg, pre, a);
-  }
+  gather_rows<N, ASSIGN, GK, NP, xpass_one_visit<N>()>(lds, sorted, beg, pre, a);
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
-  const int npairs = (ng + 1) / 2;
   const int q = tid / F::T, t = tid % F::T;
-  const bool active = q < npairs;
+  const bool active = q < NP;
   float2* T = reinterpret_cast<float2*>(lds);  // pair q uses T[q N, (q + 1) N), its two rows
   float2 d[F::E];
   if (active) {
@@ -357,31 +358,37 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     for (int e = 0; e < F::E; ++e) Tq[XSwizzle()(F::out_index(t, e))] = d[e];
   }
   __syncthreads();
-  // X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = -i (Z[k] - conj Z[N-k]) / 2
   const int Kx = a.Kx;
   const size_t row = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx;
-  for (int e = tid; e < npairs * Kx; e += blockDim.x) {
-    const int qq = e / Kx, kx = e - qq * Kx;
-    const float2 zk = T[qq * N + XSwizzle()(kx)];
-    const float2 zm = T[qq * N + XSwizzle()((N - kx) & (N - 1))];
-    const int ga = g0 + 2 * qq;
-    X[(size_t)ga * a.grid_stride + row + kx] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    if (2 * qq + 1 < ng)
-      X[(size_t)(ga + 1) * a.grid_stride + row + kx] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+  // kept rows, at their monomial index
+  for (int e = tid; e < GK * Kx; e += blockDim.x) {
+    const int j = e / Kx, kx = e - j * Kx;
+    X[(size_t)kept_monomial(j) * a.grid_stride + row + kx] = kept_spectrum<N>(T, j, kx);
+  }
+  // the rows with a power of rhat_z of 2 or more, from the identity of basis.hpp
+#pragma unroll
+  for (int dd = 0; dd < ND; ++dd) {
+    for (int kx = tid; kx < Kx; kx += blockDim.x) {
+      float2 v = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int u = 0; u < dep_terms(dd); ++u) {
+        const float2 xj = kept_spectrum<N>(T, dep_kept(dd, u), kx);
+        v.x += dep_coef(dd, u) * xj.x;
+        v.y += dep_coef(dd, u) * xj.y;
+      }
+      X[(size_t)dep_monomial(dd) * a.grid_stride + row + kx] = v;
+    }
   }
 }
 
 template <int N, int ASSIGN, int ELL>
 static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
-  constexpr int G = num_grids(ELL);
-  constexpr int SPLIT = xpass_split<N, ELL>();
-  constexpr int GB = (G + SPLIT - 1) / SPLIT;
-  constexpr int NP = (GB + 1) / 2;
+  constexpr int NP = (kept_count(ELL) + 1) / 2;
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
   const size_t shmem = rows > gather_lds_bytes<N>() ? rows : gather_lds_bytes<N>();
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL, SPLIT>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL, SPLIT>), dim3(N, p.xs, SPLIT), dim3(XGeom<N>::NT), shmem, s,
+  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL>), dim3(N, p.xs), dim3(XGeom<N>::NT), shmem, s,
                      at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
                      at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);
   return hipGetLastError();

@@ -72,7 +72,7 @@ def test_sampled_x_rows_full_size(workload):
         sub_pos, sub_w = pos[near], wp[near]
         # sum over the row of |w'| W_x W_y W_z: bounds the sum of |terms| of every grid
         l1 = est.x_transformed_row(sub_pos, np.abs(sub_w), c, (0, 0, 0), iy, iz)[0].real
-        for m in (0, 4, 17):
+        for m in (0, 4, 17, 21):   # 21 (rhat_z^4) is written from the gathered monomials
             X = pk.xgrid_view(ws, layout, m, N)
             kx = layout[m][1]
             got = X[iz, iy].cpu().numpy()
