@@ -43,6 +43,9 @@ def legendre(ell, mu):
     if ell == 4:
         m2 = mu * mu
         return (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0
+    if ell == 6:
+        m2 = mu * mu
+        return (((231.0 * m2 - 315.0) * m2 + 105.0) * m2 - 5.0) / 16.0
     raise ValueError(ell)
 
 
@@ -149,7 +152,7 @@ def amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, 
 
 def direct_multipoles(gal_pos, gal_w, ran_pos, ran_w, gal_nbar, ran_nbar, *, N, box_min, L,
                       assign, observer=(0.0, 0.0, 0.0), los=0, compensate=2, dn=1, nbins=None,
-                      norm_from=0, method="interp", chunk=512):
+                      norm_from=0, method="interp", chunk=512, ell_max=4):
     """P_ell per bin from direct amplitudes with Legendre polynomials evaluated per particle:
 
       P_ell(b) = (2 ell + 1) <Re[A_0 A_{L_ell}^*] / W^2>_b / I  -  delta_{ell 0} <N>_b / I.
@@ -171,7 +174,7 @@ def direct_multipoles(gal_pos, gal_w, ran_pos, ran_w, gal_nbar, ran_nbar, *, N, 
     pos = np.concatenate([np.asarray(gal_pos, np.float64), np.asarray(ran_pos, np.float64)])
     wprime = np.concatenate([gw, -alpha * rw])
     modes, bins = lattice_modes(N, dn, nbins)
-    ells = (0, 2, 4)
+    ells = tuple(range(0, ell_max + 1, 2))
     funcs = [lambda mu, l=l: legendre(l, mu) for l in ells]
     A = amplitudes_direct(pos, wprime, box_min, L, N, assign, observer, los, modes, funcs, method, chunk)
     p = assign

@@ -56,7 +56,7 @@ class Config:
     L: float
     observer: tuple = (0.0, 0.0, 0.0)
     assign: int = CIC          # 2 = CIC, 3 = TSC
-    ell_max: int = 4           # 0, 2 or 4
+    ell_max: int = 4           # 0, 2, 4 or 6
     los: int = 0               # 0 = per-particle LOS, 1 = fixed +z
     compensate: int = 2        # 0, 1, 2 (reading R7)
     dn: int = 1                # bin width in units of the fundamental mode
@@ -93,7 +93,9 @@ def los_monomials(ell_max):
     """Exponents (a, b, c) with a+b+c in {0, 2, .., ell_max} and their weights.
 
     (k.r)^n = sum_{a+b+c=n} n!/(a! b! c!) k_x^a k_y^b k_z^c r_x^a r_y^b r_z^c, which is
-    Eq. (10) for n = 2 (weights 1 and 2) and Eq. (12) for n = 4 (weights 1, 4, 6, 12).
+    Eq. (10) for n = 2 (weights 1 and 2) and Eq. (12) for n = 4 (weights 1, 4, 6, 12);
+    n = 6 is the next such decomposition (28 grids), which Sec. 3 notes exists for the
+    higher multipoles.
     """
     out = []
     for n in range(0, ell_max + 1, 2):
@@ -287,7 +289,9 @@ def shell_sums(A, cfg: Config, S):
 
 
 def legendre_combination(sums, cfg: Config, I):
-    """Eqs. (6)-(8): P0 = <Q0 - N>/I, P2 = 5/2 <3Q2 - Q0>/I, P4 = 9/8 <35Q4 - 30Q2 + 3Q0>/I."""
+    """Eqs. (6)-(8): P0 = <Q0 - N>/I, P2 = 5/2 <3Q2 - Q0>/I, P4 = 9/8 <35Q4 - 30Q2 + 3Q0>/I;
+    for ell = 6 the same construction, (2 ell + 1) <A_0 A_{L_ell}^*> / I with
+    L_6(mu) = (231 mu^6 - 315 mu^4 + 105 mu^2 - 5)/16: P6 = 13/16 <231Q6 - 315Q4 + 105Q2 - 5Q0>/I."""
     cnt = sums["count"].astype(np.float64)
     ok = cnt > 0
     den = np.where(ok, cnt * I, 1.0)
@@ -296,6 +300,9 @@ def legendre_combination(sums, cfg: Config, I):
         P[2] = np.where(ok, 2.5 * (3.0 * sums["Q2"] - sums["Q0"]) / den, 0.0)
     if cfg.ell_max >= 4:
         P[4] = np.where(ok, 1.125 * (35.0 * sums["Q4"] - 30.0 * sums["Q2"] + 3.0 * sums["Q0"]) / den, 0.0)
+    if cfg.ell_max >= 6:
+        P[6] = np.where(ok, (13.0 / 16.0) * (231.0 * sums["Q6"] - 315.0 * sums["Q4"] + 105.0 * sums["Q2"]
+                                             - 5.0 * sums["Q0"]) / den, 0.0)
     kf = 2.0 * np.pi / cfg.L
     k_eff = np.where(ok, kf * sums["k"] / np.where(ok, cnt, 1.0), 0.0)
     noise = np.where(ok, sums["noise"] / den, 0.0)

@@ -99,7 +99,8 @@ def test_monomial_expansion_reproduces_mu_power():
     k /= np.linalg.norm(k, axis=1)[:, None]
     r /= np.linalg.norm(r, axis=1)[:, None]
     mu = np.sum(k * r, axis=1)
-    for n in (0, 2, 4):
+    assert len(est.los_monomials(6)) == 50   # 1 + 6 + 15 + 28 grids
+    for n in (0, 2, 4, 6):
         s = np.zeros(200)
         for (a, b, c), coef in est.los_monomials(n):
             if a + b + c == n:
@@ -117,6 +118,31 @@ def test_legendre_combination_matches_printed_coefficients():
         else:
             comb = float(pref) * (c[0] * mu ** 4 + c[1] * mu ** 2 + c[2])
         np.testing.assert_allclose(comb, (2 * ell + 1) * direct.legendre(ell, mu), atol=1e-13)
+
+
+def test_legendre_six_and_its_combination():
+    """ell = 6 (not printed in the paper; the same construction as Eqs. 6-8): L_6 against
+    the library's Legendre series, its normalisation int L_6^2 = 2/13 and orthogonality
+    to mu^0..mu^4, and the combination applied to shell sums of mu^n equal to
+    13 <L_6(mu)>."""
+    from numpy.polynomial import legendre as npleg
+    mu = np.linspace(-1, 1, 81)
+    np.testing.assert_allclose(direct.legendre(6, mu), npleg.legval(mu, [0] * 6 + [1]), atol=1e-14)
+    x, wq = npleg.leggauss(12)
+    L6 = direct.legendre(6, x)
+    assert abs(np.sum(wq * L6 * L6) - 2.0 / 13.0) < 1e-14
+    for p in range(0, 5):
+        assert abs(np.sum(wq * L6 * x ** p)) < 1e-14
+    # shell sums Q_n = sum mu^n over a set of "modes", count 1 each, I = 1
+    rng = np.random.default_rng(6)
+    m = rng.uniform(-1, 1, 37)
+    sums = {"count": np.array([m.size]), "k": np.array([0.0]), "noise": np.array([0.0])}
+    for n in (0, 2, 4, 6):
+        sums["Q%d" % n] = np.array([np.sum(m ** n)])
+    cfg = est.Config(N=8, box_min=(0, 0, 0), L=1.0, ell_max=6, nbins=1)
+    _, P, _ = est.legendre_combination(sums, cfg, 1.0)
+    for ell in (2, 4, 6):
+        assert abs(P[ell][0] - (2 * ell + 1) * np.mean(direct.legendre(ell, m))) < 1e-12
 
 
 # --------------------------------------------------------------------------- assignment
@@ -191,19 +217,21 @@ def test_grid_identities():
 
 # --------------------------------------------------------------------------- cross-paths
 
-@pytest.mark.parametrize("assign,N,los,comp", [(2, 8, 0, 2), (3, 8, 0, 2), (2, 16, 0, 1),
-                                               (3, 16, 0, 0), (2, 8, 1, 2)])
-def test_fft_path_equals_interpolated_phase_sum(assign, N, los, comp):
+@pytest.mark.parametrize("assign,N,los,comp,ell_max", [(2, 8, 0, 2, 4), (3, 8, 0, 2, 4), (2, 16, 0, 1, 4),
+                                                       (3, 16, 0, 0, 4), (2, 8, 1, 2, 4), (2, 8, 0, 2, 6),
+                                                       (3, 16, 0, 2, 6)])
+def test_fft_path_equals_interpolated_phase_sum(assign, N, los, comp, ell_max):
     """Sec. 3: the decomposition is exact, so the gridded estimator equals the
-    direct sum over particles with interpolated phases and Legendre weights."""
-    gal, ran, cfg = _small_case(N=N, assign=assign, los=los, compensate=comp)
+    direct sum over particles with interpolated phases and Legendre weights (for
+    ell = 6 too, with its 28 degree-6 grids)."""
+    gal, ran, cfg = _small_case(N=N, assign=assign, los=los, compensate=comp, ell_max=ell_max)
     r = _run(gal, ran, cfg)
     d = direct.direct_multipoles(gal.pos, gal.w, ran.pos, ran.w, gal.nbar, ran.nbar, N=N,
                                  box_min=cfg.box_min, L=cfg.L, assign=assign, los=los,
-                                 compensate=comp, method="interp")
+                                 compensate=comp, method="interp", ell_max=ell_max)
     np.testing.assert_array_equal(r.nmodes, d["count"])
     scale = np.max(np.abs(r.P[0]) + r.noise)
-    for ell in (0, 2, 4):
+    for ell in range(0, ell_max + 1, 2):
         np.testing.assert_allclose(r.P[ell], d[ell], rtol=0, atol=1e-11 * scale)
     np.testing.assert_allclose(r.k_eff, d["k_eff"], rtol=1e-13)
 
@@ -261,7 +289,7 @@ def test_sum_over_galaxies_close_at_low_k():
 def test_plane_parallel_reduction():
     """With the LOS fixed to z, the 22-grid estimator equals the single-FFT plane-parallel
     estimator (2l+1) <|A0|^2 L_l(k_z/k)> / I (minus the noise for l = 0)."""
-    gal, ran, cfg = _small_case(N=16, los=1, assign=3)
+    gal, ran, cfg = _small_case(N=16, los=1, assign=3, ell_max=6)
     r = _run(gal, ran, cfg)
     alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
     pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
@@ -275,7 +303,7 @@ def test_plane_parallel_reduction():
     C = np.prod(Ci[modes % 16], axis=1)
     q = np.abs(A0[idx]) ** 2 / W2
     cnt = np.bincount(bins, minlength=8)
-    for ell in (0, 2, 4):
+    for ell in (0, 2, 4, 6):
         v = np.bincount(bins, weights=(2 * ell + 1) * q * direct.legendre(ell, mu), minlength=8)
         if ell == 0:
             v = v - np.bincount(bins, weights=S * C / W2, minlength=8)
