@@ -10,6 +10,9 @@
  *                     its own line of sight rhat = (x - observer)/|x - observer|;
  *   Sec. 3, Eqs. (9)-(13)  A_2 and A_4 from the FFTs of 6 and 15 grids F rhat_i rhat_j
  *                     and F rhat_i^2 rhat_j rhat_l (1, 7 or 22 FFTs for ell_max 0, 2, 4);
+ *                     ell_max = 6 adds A_6 from the 28 degree-6 grids (the higher-order
+ *                     decomposition Sec. 3 mentions) and P_6 = 13/(16 I)
+ *                     <A_0 (231 A_6 - 315 A_4 + 105 A_2 - 5 A_0)^*>;
  *   Sec. 3, Eqs. (6)-(8)   P_0 = <|A_0|^2>/I - noise, P_2 = 5/(2I) <A_0 (3A_2 - A_0)^*>,
  *                     P_4 = 9/(8I) <A_0 (35 A_4 - 30 A_2 + 3 A_0)^*>, shell-averaged;
  *   Sec. 2, Eq. (3)   shot noise subtracted from ell = 0 only;
@@ -52,7 +55,7 @@ typedef int32_t pk_status;
 #define PK_EDOM (-3)        /* non-finite xyz / w / nbar, a particle at the observer, sum_r w = 0, I <= 0 */
 #define PK_EWORKSPACE (-4)  /* workspace null or smaller than pk_workspace_size() */
 #define PK_EDEVICE (-5)     /* a HIP runtime error */
-#define PK_ENOTSUP (-6)     /* N not a supported FFT size, or more than 2^31 - 1 particles */
+#define PK_ENOTSUP (-6)     /* N not a supported FFT size, ell_max = 6 at N = 2048, or more than 2^31 - 1 particles */
 
 #define PK_CIC 2
 #define PK_TSC 3
@@ -75,7 +78,7 @@ typedef struct {
 typedef struct {
   int32_t N;           /* grid side: 8, 16, 32, 64, 128, 256, 512, 1024 or 2048 */
   int32_t assign;      /* PK_CIC or PK_TSC */
-  int32_t ell_max;     /* 0, 2 or 4 -> 1, 7 or 22 LOS-weighted grids */
+  int32_t ell_max;     /* 0, 2, 4 or 6 -> 1, 7, 22 or 50 LOS-weighted grids (6: N <= 1024) */
   int32_t los;         /* 0: each particle's own line of sight; 1: fixed +z (plane-parallel) */
   int32_t compensate;  /* 0, 1 or 2 (see above) */
   int32_t dn;          /* bin width in units of the fundamental mode 2 pi / L, >= 1 */
@@ -85,7 +88,7 @@ typedef struct {
   double L;            /* side of the cube */
   double observer[3];  /* origin of the lines of sight */
   int32_t x_planes;    /* z planes per slab of the x and y transforms: 0 = automatic (all
-                        * N planes while the 1, 7 or 22 x-transformed grids, 8 G N^2 Kx bytes
+                        * N planes while the 1, 7, 22 or 50 x-transformed grids, 8 G N^2 Kx bytes
                         * with Kx = nbins dn rounded up to the kx tile, take at most 128 GiB,
                         * i.e. every N up to 1024; otherwise the largest power of two of
                         * planes whose two slabs fit in 8 GiB), or a power of two <= N. With
@@ -99,13 +102,13 @@ typedef struct {
 
 /* Results (host memory, caller-owned arrays).
  *   k_eff[nbins]   mode-averaged |k| of each bin (0 for an empty bin)
- *   P[(ell_max/2 + 1) * nbins]  P_0 then P_2 then P_4, bin-fastest (0 for an empty bin)
+ *   P[(ell_max/2 + 1) * nbins]  P_0 then P_2, P_4 (and P_6), bin-fastest (0 for an empty bin)
  *   noise[nbins]   shell mean of the noise subtracted from P_0, divided by I
  *   nmodes[nbins]  number of modes of the full N^3 lattice in each bin
  *   wedges[2][nbins]  P_perp (mu in [0, 1/2]) then P_par (mu in [1/2, 1]) from the
  *                  multipoles, the wedges of Sec. 5: P_0 -+ 3/8 P_2 +- 15/128 P_4 (the
  *                  top-hat means of L_2 and L_4 over the two ranges); multipoles above
- *                  ell_max are taken as 0
+ *                  ell_max are taken as 0, and P_6 is not used (the paper's form)
  * Scalars alpha, I and S (sum_g w^2 + alpha^2 sum_r w^2) are filled in. Any array
  * pointer may be NULL to skip it. On error nothing is written. */
 typedef struct {
@@ -258,7 +261,7 @@ pk_status pk_mlp_train_step(const pk_mlp_shape* shape, void* state, const float*
                             float lr, int32_t step, float* d_loss, void* workspace, size_t workspace_bytes,
                             void* hip_stream);
 
-/* Number of LOS-weighted grids for ell_max (1, 7, 22), and the exponents of grid m. */
+/* Number of LOS-weighted grids for ell_max (1, 7, 22, 50), and the exponents of grid m. */
 int32_t pk_num_grids(int32_t ell_max);
 pk_status pk_monomial(int32_t m, int32_t* a, int32_t* b, int32_t* c);
 

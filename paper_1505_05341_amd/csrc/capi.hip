@@ -19,7 +19,8 @@ static pk_status fail(pk_status st, const std::string& why) {
   return st;
 }
 
-static int num_grids_for(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
+static int num_grids_for(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : (ell == 4 ? 22 : 50)); }
+static bool ell_ok(int ell) { return ell == 0 || ell == 2 || ell == 4 || ell == 6; }
 
 static int64_t isqrt64(int64_t n) {
   if (n <= 0) return 0;
@@ -55,7 +56,7 @@ static int auto_slab(int N, int G, int Kx) {
 struct Schedule {
   int y, z;
 };
-static Schedule g_sched[12][3];
+static Schedule g_sched[12][4];
 
 static int log2_of(int N) {
   int l = 0;
@@ -86,7 +87,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.n_ran = n_ran;
   if (!supported_N(p.N)) return fail(PK_ENOTSUP, "N must be one of 8, 16, 32, 64, 128, 256, 512, 1024, 2048");
   if (p.assign != PK_CIC && p.assign != PK_TSC) return fail(PK_EINVAL, "assign must be 2 (CIC) or 3 (TSC)");
-  if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(PK_EINVAL, "ell_max must be 0, 2 or 4");
+  if (!ell_ok(p.ell_max)) return fail(PK_EINVAL, "ell_max must be 0, 2, 4 or 6");
   if (p.los != 0 && p.los != 1) return fail(PK_EINVAL, "los must be 0 or 1");
   if (p.compensate < 0 || p.compensate > 2) return fail(PK_EINVAL, "compensate must be 0, 1 or 2");
   if (p.norm_from != 0 && p.norm_from != 1) return fail(PK_EINVAL, "norm_from must be 0 or 1");
@@ -97,6 +98,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
     if (!isfinite(p.box_min[i]) || !isfinite(p.observer[i])) return fail(PK_EINVAL, "box_min and observer must be finite");
   if (n_gal < 0 || n_ran < 0) return fail(PK_EINVAL, "catalogue sizes must be >= 0");
   if (n_gal + n_ran > (int64_t)0x7fffffff) return fail(PK_ENOTSUP, "at most 2^31 - 1 particles per call");
+  if (p.ell_max == 6 && p.N > 1024) return fail(PK_ENOTSUP, "ell_max = 6 is built for N <= 1024");
   if (cfg->x_planes < 0 || cfg->x_planes > p.N || (cfg->x_planes & (cfg->x_planes - 1)) != 0)
     return fail(PK_EINVAL, "x_planes must be 0 (automatic) or a power of two <= N");
 
@@ -138,7 +140,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
       for (int m = 0; m < p.G; ++m) {
         const Monomial mo = monomial(m);
         if (mo.a + mo.b + mo.c != n || mo.c != c) continue;
-        static const int fact[5] = {1, 1, 2, 6, 24};
+        static const int fact[7] = {1, 1, 2, 6, 24, 120, 720};
         const int s = gt.count[g]++;
         gt.grid[g][s] = m;
         gt.a[g][s] = mo.a;
@@ -372,7 +374,7 @@ pk_status pk_workspace_size(const pk_config* cfg, int64_t n_gal, int64_t n_ran, 
 }
 
 int64_t pk_result_doubles(const pk_config* cfg) {
-  if (!cfg || (cfg->ell_max != 0 && cfg->ell_max != 2 && cfg->ell_max != 4) || cfg->nbins < 1) return -1;
+  if (!cfg || !ell_ok(cfg->ell_max) || cfg->nbins < 1) return -1;
   return result_size(cfg->nbins, cfg->ell_max / 2 + 1);
 }
 
@@ -407,7 +409,7 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
 // ------------------------------------------------------------------- FFT schedules
 
 static bool schedule_key_ok(int32_t N, int32_t ell_max) {
-  return supported_N(N) && (ell_max == 0 || ell_max == 2 || ell_max == 4);
+  return supported_N(N) && ell_ok(ell_max);
 }
 
 pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t z_values) {
@@ -694,7 +696,7 @@ int32_t pk_stage_times(double* ms, int32_t n) {
 const char* pk_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : "?"; }
 
 int32_t pk_num_grids(int32_t ell_max) {
-  return (ell_max == 0 || ell_max == 2 || ell_max == 4) ? num_grids_for(ell_max) : -1;
+  return ell_ok(ell_max) ? num_grids_for(ell_max) : -1;
 }
 
 pk_status pk_monomial(int32_t m, int32_t* a, int32_t* b, int32_t* c) {

@@ -9,16 +9,16 @@
 
 namespace pk {
 
-constexpr int kMaxGrids = 22;
-constexpr int kMaxGroups = 9;
-constexpr int kMaxMembers = 5;
+constexpr int kMaxGrids = 50;       // 1 + 6 + 15 + 28 monomial grids (ell_max = 6)
+constexpr int kMaxGroups = 16;      // z-power groups: 1 + 3 + 5 + 7
+constexpr int kMaxMembers = 7;
 constexpr int kMaxTiles = 256;      // kx tiles: 16 columns up to N = 512, 8 at 1024, 4 at 2048
 constexpr int kStatsBlocks = 2048;  // blocks of the catalogue-scalar reduction
 constexpr int kScanChunk = 4096;    // counters per scan block
 constexpr int kScanTopMax = 4096;   // scan blocks of one scan (N^2 kRowHistParts / kScanChunk at N = 2048)
 constexpr int kSortBlocks = 2048;   // level-A sort blocks (one contiguous particle range each)
 constexpr int kRowHistParts = 4;    // level-B blocks per plane
-constexpr int kNumSums = 6;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise
+constexpr int kNumSums = 7;         // per-bin sums: count, |n|, Q0, Q2, Q4, noise, Q6
 
 // Device scalars written by the catalogue-scalar kernels.
 enum ScalarSlot {
@@ -32,13 +32,13 @@ enum FlagBits {
   kFlagBadNorm = 16
 };
 
-// Exponents of monomial m in the fixed order used everywhere: degree 0, then degree 2,
-// then degree 4, each with the power of x descending, then the power of y descending.
+// Exponents of monomial m in the fixed order used everywhere: degree 0, 2, 4, then 6,
+// each with the power of x descending, then the power of y descending.
 struct Monomial { int a, b, c; };
 __host__ __device__ inline Monomial monomial(int m) {
-  // degree 0: m = 0; degree 2: m = 1..6; degree 4: m = 7..21
-  int n = m == 0 ? 0 : (m <= 6 ? 2 : 4);
-  int r = m == 0 ? 0 : (m <= 6 ? m - 1 : m - 7);
+  // degree 0: m = 0; degree 2: m = 1..6; degree 4: m = 7..21; degree 6: m = 22..49
+  int n = m == 0 ? 0 : (m <= 6 ? 2 : (m <= 21 ? 4 : 6));
+  int r = m == 0 ? 0 : (m <= 6 ? m - 1 : (m <= 21 ? m - 7 : m - 22));
   for (int a = n; a >= 0; --a) {
     for (int b = n - a; b >= 0; --b) {
       if (r == 0) return Monomial{a, b, n - a - b};

@@ -39,22 +39,8 @@ struct XArgs {
   int64_t grid_stride;  // float2 elements per grid of X: xr * xs * N * Kx
 };
 
-__host__ __device__ constexpr int num_grids(int ell) { return ell == 0 ? 1 : (ell == 2 ? 7 : 22); }
 
-// The gathered monomials rhat^m (power of rhat_z at most 1) in kept order (basis.hpp):
-// 1; xx xy xz yy yz; xx.xx xx.xy xx.xz xx.yy xx.yz xy.yy xy.yz yy.yy yy.yz.
-template <int GK>
-__device__ __forceinline__ void kept_monomials(float rx, float ry, float rz, float (&m)[GK]) {
-  m[0] = 1.0f;
-  if constexpr (GK > 1) {
-    const float xx = rx * rx, xy = rx * ry, xz = rx * rz, yy = ry * ry, yz = ry * rz;
-    m[1] = xx; m[2] = xy; m[3] = xz; m[4] = yy; m[5] = yz;
-    if constexpr (GK > 6) {
-      m[6] = xx * xx;  m[7] = xx * xy;  m[8] = xx * xz;  m[9] = xx * yy;  m[10] = xx * yz;
-      m[11] = xy * yy; m[12] = xy * yz; m[13] = yy * yy; m[14] = yy * yz;
-    }
-  }
-}
+
 
 // Block geometry: 512 threads and chunks of 1024 particles up to N = 512; from N = 1024 on,
 // blocks of 1024 threads (one cell per thread at 1024, two at 2048) and chunks of 2048.
@@ -288,9 +274,10 @@ struct XSwizzle {
 
 // Waves per SIMD the registers are budgeted for: 8 (4 blocks of 512 threads per CU, which
 // the 32 KB of LDS of the 15 gathered rows allow; <= 64 VGPRs, measured 11% faster than 6)
-// up to N = 512, 4 (one block of 1024 threads) from 1024 on.
-template <int N>
-constexpr int xpass_waves() { return N >= 1024 ? 4 : 8; }
+// up to N = 512, 4 (one block of 1024 threads) from 1024 on; 4 for the 28 gathered rows of
+// ell_max = 6 at every N.
+template <int N, int ELL>
+constexpr int xpass_waves() { return (N >= 1024 || ELL >= 6) ? 4 : 8; }
 
 // x-transformed value at kx of kept row j, from the packed spectra in LDS: rows (2q, 2q+1)
 // were transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
@@ -304,7 +291,7 @@ __device__ __forceinline__ float2 kept_spectrum(const float2* T, int j, int kx) 
 }
 
 template <int N, int ASSIGN, int ELL>
-__global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
+__global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
   constexpr int GK = kept_count(ELL);   // gathered and transformed rows
   constexpr int ND = dep_count(ELL);    // rows written as their combinations
@@ -399,6 +386,9 @@ static hipError_t launch_x2(const Plan& p, char* ws, const XArgs& a, hipStream_t
   switch (p.ell_max) {
     case 0: return launch_x3<N, ASSIGN, 0>(p, ws, a, s);
     case 2: return launch_x3<N, ASSIGN, 2>(p, ws, a, s);
+    case 6:   // 14 row pairs of 2048 cells would need 1792 threads: built up to N = 1024
+      if constexpr (N <= 1024) return launch_x3<N, ASSIGN, 6>(p, ws, a, s);
+      else return hipErrorInvalidValue;
     default: return launch_x3<N, ASSIGN, 4>(p, ws, a, s);
   }
 }

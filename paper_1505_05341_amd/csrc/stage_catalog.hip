@@ -624,7 +624,8 @@ hipError_t launch_sort(const Plan& p, const pk_catalog& gal, const pk_catalog& r
 // --------------------------------------------------------------------------------
 // Final reduction (Sec. 3, Eqs. 6-8): per-bin sums over the z-pass blocks in block
 // order, then the Legendre combinations, the noise on ell = 0 only and 1/I.
-// Result layout: k_eff[nb], P[(ell_max/2+1) nb], noise[nb], nmodes[nb], alpha, I, S, flags.
+// Result layout: k_eff[nb], P[(ell_max/2+1) nb], noise[nb], nmodes[nb], wedges[2 nb],
+// alpha, I, S, flags.
 // --------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int zblocks, int nbins, int ell_max,
                                                        double kf, const double* scal, const int* flags,
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
   // a fixed tree combines them
   __shared__ double red[kNumSums][256];
   const int b = blockIdx.x, t = threadIdx.x;
-  double s[kNumSums] = {0, 0, 0, 0, 0, 0};
+  double s[kNumSums] = {};
   for (int blk = t; blk < zblocks; blk += 256) {
     const double* q = zpart + ((size_t)blk * nbins + b) * kNumSums;
 #pragma unroll
@@ -665,6 +666,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* zpart, int 
     P[b] = (red[2][0] - red[5][0]) / den;
     if (nl > 1) P[nbins + b] = 2.5 * (3.0 * red[3][0] - red[2][0]) / den;
     if (nl > 2) P[2 * nbins + b] = 1.125 * (35.0 * red[4][0] - 30.0 * red[3][0] + 3.0 * red[2][0]) / den;
+    // ell = 6 by the same construction: 13/16 (231 Q6 - 315 Q4 + 105 Q2 - 5 Q0), from L_6
+    if (nl > 3)
+      P[3 * nbins + b] =
+          0.8125 * (231.0 * red[6][0] - 315.0 * red[4][0] + 105.0 * red[3][0] - 5.0 * red[2][0]) / den;
     noise[b] = red[5][0] / den;
     // wedges mu in [0, 1/2] and [1/2, 1] from the multipoles (Sec. 5): the top-hat means
     // of L_2 and L_4 over those ranges are -+3/8 and +-15/128 (missing multipoles are 0)

@@ -7,8 +7,8 @@
 //   z) are summed in registers, so each group leaves a single grid H_{n,c}. Only the
 //   rows with kx0^2 + ky^2 < K^2 are stored (kx0 = the tile's smallest kx).
 // z pass: a persistent block walks (kx tile, ky) columns. It transforms H_{0,0}
-//   along z to A_0, accumulates A_2 = |t|^-2 sum_c tz^c FFT_z[H_{2,c}] and
-//   A_4 = |t|^-4 sum_c tz^c FFT_z[H_{4,c}] (t = 2n/N), and adds per mode
+//   along z to A_0, accumulates A_n = |t|^-n sum_c tz^c FFT_z[H_{n,c}] for n = 2, 4
+//   (and 6) (t = 2n/N), and adds per mode
 //   mu Re[A_0 A_l^*] / W^2, the noise and the mode count to FP64 bin sums in LDS
 //   (mu = 1 on the kx = 0 plane, 2 elsewhere: the other half of the lattice holds the
 //   complex conjugates). Each block writes its bin sums once.
@@ -290,7 +290,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
           const float2 A2 = acc[e];
           w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
         }
-        // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise
+        // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise, 6 Q6
         bin_add<4>(bins, b, valid, w4, 0);
         double w1[1] = {mu * S * (double)noise_f};
         bin_add<1>(bins, b, valid, w1, 5);
@@ -314,6 +314,27 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const float2 A4 = acc[e];
         double w[1] = {mu * (double)((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw)};
         bin_add<1>(bins, b, valid, w, 4);
+      }
+    }
+    if (ELL >= 6) {
+      // A_6 = |t|^-6 sum_c tz^c FFT_z[H_(6,c)], groups 9 .. 15
+      z_horner<N, TK, EC, 6>(base, a.h_group_stride, 9, zstride, c, t, tw, T, acc);
+      const int tt = col_hide<EC>(t);
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) {
+        const int kzi = F::out_index(tt, e);
+        const int kz = signed_freq<N>(kzi);
+        const int n2 = n2xy + kz * kz;
+        const bool valid = n2 > 0 && n2 < a.K2;
+        const int b = valid ? isqrt_i(n2) / a.dn : 0;
+        const float iw = a.compensate >= 1 ? wxy * invw2[kzi] : 1.0f;
+        const float tz = (float)kz * twoN;
+        const float t2 = tx * tx + ty * ty + tz * tz;
+        const float inv_t6 = 1.0f / (t2 * t2 * t2);
+        const float2 z0 = a0[e];
+        const float2 A6 = acc[e];
+        double w[1] = {mu * (double)((z0.x * A6.x + z0.y * A6.y) * inv_t6 * iw)};
+        bin_add<1>(bins, b, valid, w, 6);
       }
     }
   }
@@ -360,6 +381,9 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
   switch (p.ell_max) {
     case 0: return launch_z3<N, TK, 0>(p, ws, a, s);
     case 2: return launch_z3<N, TK, 2>(p, ws, a, s);
+    case 6:
+      if constexpr (N <= 1024) return launch_z3<N, TK, 6>(p, ws, a, s);
+      else return hipErrorInvalidValue;
     default: return launch_z3<N, TK, 4>(p, ws, a, s);
   }
 }

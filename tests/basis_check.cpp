@@ -1,42 +1,50 @@
-// Host check of the reduced-basis table: for random unit vectors, every dependent
-// monomial equals its combination of kept monomials (built with -D__host__= -D__device__=).
+// Host check of the reduced-basis header: the gathered monomials have a power of rhat_z of
+// at most 1, kept_monomials evaluates them, and for random unit vectors every dependent
+// monomial equals its combination of gathered ones (built with -D__host__= -D__device__=).
 #include <cmath>
 #include <cstdio>
 #include <random>
+#include <vector>
 
 #include "basis.hpp"
 
-static double mono(int a, int b, int c, const double* r) { return std::pow(r[0], a) * std::pow(r[1], b) * std::pow(r[2], c); }
+struct E3 { int a, b, c; };
 
 int main() {
-  // exponents of the 22 monomials in the library order
-  const int E[22][3] = {{0, 0, 0}, {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}, {4, 0, 0},
-                        {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0}, {1, 2, 1}, {1, 1, 2},
-                        {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3}, {0, 0, 4}};
-  std::mt19937_64 g(1505);
-  std::normal_distribution<double> n(0.0, 1.0);
-  double worst = 0.0;
+  // exponents of the 50 monomials in the library order: degree 0, 2, 4, 6; x power
+  // descending, then y power descending
+  std::vector<E3> E;
+  for (int n = 0; n <= 6; n += 2)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) E.push_back({a, b, n - a - b});
   int bad = 0;
-  for (int j = 0; j < pk::kept_count(4); ++j)
-    if (E[pk::kept_monomial(j)][2] > 1) ++bad;  // kept ones have c <= 1
-  for (int d = 0; d < pk::dep_count(4); ++d)
-    if (E[pk::dep_monomial(d)][2] < 2) ++bad;   // dependent ones have c >= 2
-  if (pk::kept_count(2) != 6 || pk::dep_count(2) != 1 || pk::dep_monomial(0) != 6) ++bad;
+  if (E.size() != 50) ++bad;
+  const int ells[4] = {0, 2, 4, 6}, total[4] = {1, 7, 22, 50};
+  for (int i = 0; i < 4; ++i) {
+    const int l = ells[i];
+    if (pk::kept_count(l) + pk::dep_count(l) != total[i]) ++bad;
+    for (int j = 0; j < pk::kept_count(l); ++j)
+      if (E[pk::kept_monomial(j)].c > 1 || E[pk::kept_monomial(j)].a + E[pk::kept_monomial(j)].b + E[pk::kept_monomial(j)].c > l) ++bad;
+    for (int d = 0; d < pk::dep_count(l); ++d)
+      if (E[pk::dep_monomial(d)].c < 2) ++bad;
+  }
+  std::mt19937_64 g(1505);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  double worst = 0.0, worst_m = 0.0;
   for (int it = 0; it < 1000; ++it) {
-    double r[3] = {n(g), n(g), n(g)};
+    double r[3] = {nd(g), nd(g), nd(g)};
     const double s = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
     for (double& v : r) v /= s;
-    for (int d = 0; d < pk::dep_count(4); ++d) {
-      const int* e = E[pk::dep_monomial(d)];
+    auto mono = [&](const E3& e) { return std::pow(r[0], e.a) * std::pow(r[1], e.b) * std::pow(r[2], e.c); };
+    float m[28];
+    pk::kept_monomials<28>((float)r[0], (float)r[1], (float)r[2], m);
+    for (int j = 0; j < 28; ++j) worst_m = std::fmax(worst_m, std::fabs(m[j] - mono(E[pk::kept_monomial(j)])));
+    for (int d = 0; d < pk::dep_count(6); ++d) {
       double sum = 0.0;
-      for (int t = 0; t < pk::dep_terms(d); ++t) {
-        const int* k = E[pk::kept_monomial(pk::dep_kept(d, t))];
-        sum += pk::dep_coef(d, t) * mono(k[0], k[1], k[2], r);
-      }
-      const double err = std::fabs(sum - mono(e[0], e[1], e[2], r));
-      if (err > worst) worst = err;
+      for (int t = 0; t < pk::dep_terms(d); ++t) sum += pk::dep_coef(d, t) * mono(E[pk::kept_monomial(pk::dep_kept(d, t))]);
+      worst = std::fmax(worst, std::fabs(sum - mono(E[pk::dep_monomial(d)])));
     }
   }
-  std::printf("bad=%d worst=%.3e\n", bad, worst);
-  return (bad == 0 && worst < 1e-13) ? 0 : 1;
+  std::printf("bad=%d identity=%.3e monomials=%.3e\n", bad, worst, worst_m);
+  return (bad == 0 && worst < 1e-13 && worst_m < 1e-6) ? 0 : 1;
 }

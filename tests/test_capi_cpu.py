@@ -26,10 +26,10 @@ def test_library_exports_every_declared_function():
 
 
 def test_monomial_table_matches_degrees():
-    assert [native.num_grids(e) for e in (0, 2, 4)] == [1, 7, 22]
-    monos = [native.monomial(m) for m in range(22)]
-    assert len(set(monos)) == 22
-    assert [sum(m) for m in monos] == [0] + [2] * 6 + [4] * 15
+    assert [native.num_grids(e) for e in (0, 2, 4, 6)] == [1, 7, 22, 50]
+    monos = [native.monomial(m) for m in range(50)]
+    assert len(set(monos)) == 50
+    assert [sum(m) for m in monos] == [0] + [2] * 6 + [4] * 15 + [6] * 28
 
 
 def cfg(**kw):
@@ -51,7 +51,8 @@ def test_workspace_size_grows_with_particles_and_grid():
     (dict(N=48), -6), (dict(N=4096, nbins=8), -6), (dict(ell_max=3), -1), (dict(assign=1), -1),
     (dict(los=2), -1), (dict(compensate=3), -1), (dict(dn=0), -1), (dict(nbins=33), -1),
     (dict(nbins=0), -1), (dict(L=-1.0), -1), (dict(norm_from=2), -1),
-    (dict(x_planes=3), -1), (dict(x_planes=128), -1), (dict(x_planes=-2), -1),
+    (dict(x_planes=3), -1), (dict(x_planes=128), -1), (dict(x_planes=-2), -1), (dict(ell_max=8), -1),
+    (dict(N=2048, nbins=8, ell_max=6), -6),
 ])
 def test_bad_configurations(kw, code):
     c = native.make_config(cfg(**kw))
@@ -80,6 +81,8 @@ def test_status_strings_and_result_size():
     import ctypes
     # k_eff, P0 P2 P4, noise, nmodes, two wedges per bin + alpha, I, S, flags
     assert lib.pk_result_doubles(ctypes.byref(c)) == 32 * 8 + 4
+    c6 = native.make_config(cfg(ell_max=6))
+    assert lib.pk_result_doubles(ctypes.byref(c6)) == 32 * 9 + 4
 
 
 def test_slab_plans():

@@ -142,6 +142,44 @@ def test_xgrid_rows_match_oracle(pk):
             assert err < 1e-5, (m, iy, iz, err)
 
 
+@pytest.mark.parametrize("N,assign,los,kind", [(32, 2, 0, "tiny"), (64, 3, 0, "clustered"), (32, 2, 1, "tiny"),
+                                               (64, 2, 0, "clustered")])
+def test_ell6_matches_oracle(pk, N, assign, los, kind):
+    """ell_max = 6: 50 monomial grids (28 gathered, 22 from the identity), 16 z-power
+    groups, P6 from L_6; the whole estimator against the oracle."""
+    if kind == "tiny":
+        gal, ran, cfg = catalogs.tiny_plain(N=N, assign=assign, los=los, ell_max=6)
+    else:
+        gal, ran, cfg = catalogs.small_clustered(N=N, nbar=3e-4, ran_factor=10.0, assign=assign, los=los, ell_max=6)
+    got, ref = run_both(pk, gal, ran, cfg)
+    assert "P6" in got
+    compare(got, ref, cfg)
+
+
+def test_ell6_xgrid_rows(pk):
+    """All 50 x-transformed rows at ell_max = 6 (the degree-6 rows with a power of rhat_z
+    of 2 or more come from up to 10 gathered rows each) against the oracle's rows."""
+    from paper_1505_05341_amd import native
+    gal, ran, cfg = catalogs.small_clustered(N=32, nbar=3e-4, ran_factor=10.0, assign=3, ell_max=6)
+    g = pk.DeviceCatalog.from_host(gal)
+    r = pk.DeviceCatalog.from_host(ran)
+    ws, layout = pk.stage_xgrids(g, r, cfg)
+    assert len(layout) == 50
+    c = est.Config(**cfg)
+    alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    wp = est.signed_weights(gal.w, ran.w, alpha)
+    rng = np.random.default_rng(6)
+    iy, iz = (int(v) for v in rng.integers(0, c.N, 2))
+    l1 = est.x_transformed_row(pos, np.abs(wp), c, (0, 0, 0), iy, iz)[0].real
+    for m in range(50):
+        X = pk.xgrid_view(ws, layout, m, c.N).cpu().numpy()
+        kx = layout[m][1]
+        ref = est.x_transformed_row(pos, wp, c, native.monomial(m), iy, iz)[:kx]
+        err = np.max(np.abs(X[iz, iy, :, 0] + 1j * X[iz, iy, :, 1] - ref)) / l1
+        assert err < 1e-5, (m, err)
+
+
 def test_repeat_runs_agree(pk):
     gal, ran, cfg = catalogs.small_clustered(N=64, nbar=3e-4, ran_factor=10.0)
     g = pk.DeviceCatalog.from_host(gal)
