@@ -150,6 +150,17 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
     }
   }
 
+  gt.nmem = 0;
+  for (int g = 0; g < gt.ngroups; ++g) {
+    for (int s = gt.count[g] - 1; s >= 0; --s) {
+      gt.mgrid[gt.nmem] = gt.grid[g][s];
+      gt.ma[gt.nmem] = gt.a[g][s];
+      gt.mcoef[gt.nmem] = gt.coef[g][s];
+      ++gt.nmem;
+    }
+    gt.mend[g] = gt.nmem;
+  }
+
   const int nl = p.ell_max / 2 + 1;
   p.result_doubles = result_size(p.nbins, nl);
   const int64_t nrow = (int64_t)p.N * p.N;

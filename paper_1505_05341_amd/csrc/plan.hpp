@@ -61,6 +61,13 @@ struct GroupTable {
   int a[kMaxGroups][kMaxMembers];
   int b[kMaxGroups][kMaxMembers];
   float coef[kMaxGroups][kMaxMembers];
+  // the same members flattened in the order the y pass takes them (group by group,
+  // largest power of y first); group g ends before member mend[g]
+  int nmem;
+  int mgrid[kMaxGrids];
+  int ma[kMaxGrids];
+  float mcoef[kMaxGrids];
+  int mend[kMaxGroups];
 };
 
 // Tile table of the y and z passes: per kx tile the largest |ky| kept (M), the

@@ -73,43 +73,72 @@ __device__ __forceinline__ int col_hide(int v) {
   return v;
 }
 
+// Loads the column tile of member grid m (plane pbase + zs of X) in stage-0 order.
+template <int N, int TK, int EC>
+__device__ __forceinline__ void load_member(const float2* __restrict__ X, const YArgs& a, int m, int zs, int kt,
+                                            int tid0, float2 (&d)[Fft<N, EC>::E]) {
+  using F = Fft<N, EC>;
+  const int tid = col_hide<EC>(tid0);
+  const int c = tid % TK, t = tid / TK;
+  const float2* __restrict__ src =
+      X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + kt * TK + c;
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * a.Kx];
+}
+
 template <int N, int TK, int EC>
 __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
                                                                   const float2* __restrict__ tw, const YArgs a) {
   using F = Fft<N, EC>;
   extern __shared__ float2 T[];
+  // The flattened member table and the twiddles, in LDS: loads of global memory retire
+  // in order, so reading either from global memory inside a transform would also wait
+  // for the next member's tile, which is in flight meanwhile.
+  float2* twl = T + TK * N;
+  __shared__ int s_grid[kMaxGrids], s_pa[kMaxGrids], s_end[kMaxGroups];
+  __shared__ float s_coef[kMaxGrids];
   const int tid0 = threadIdx.x;
   const uint32_t nblk = gridDim.x * gridDim.y;
   const uint32_t lb = xcd_group(blockIdx.x + blockIdx.y * gridDim.x, nblk);
   const int kt = (int)(lb % gridDim.x), zs = (int)(lb / gridDim.x), z = a.z0 + zs;
   const GroupTable& gt = *a.gt;
+  const int nmem = gt.nmem, ngroups = gt.ngroups;
+  for (int i = tid0; i < nmem; i += blockDim.x) {
+    s_grid[i] = gt.mgrid[i];
+    s_pa[i] = gt.ma[i];
+    s_coef[i] = gt.mcoef[i];
+  }
+  for (int i = tid0; i < ngroups; i += blockDim.x) s_end[i] = gt.mend[i];
+  for (int i = tid0; i < N; i += blockDim.x) twl[i] = tw[i];
   const int M = a.tt->M[kt];
   const int64_t regoff = a.tt->regoff[kt];
   const int nslot = 2 * M + 1;
-  const int Kx = a.Kx;
   // the EC = 16 schedule keeps the ty of its values in registers
   float tyv[F::E];
 #pragma unroll
   for (int e = 0; e < F::E; ++e) tyv[e] = (float)signed_freq<N>(F::out_index(tid0 / TK, e)) * (2.0f / N);
-  const int ngroups = gt.ngroups;
+  __syncthreads();
+  // member j + 1 is loaded while member j is transformed
+  float2 nd[F::E];
+  load_member<N, TK, EC>(X, a, s_grid[0], zs, kt, tid0, nd);
+  int j = 0;
   for (int g = 0; g < ngroups; ++g) {
     // Horner in ty over the members, whose powers of y run 0, 1, .., n - c:
     // acc <- acc ty + coef tx^a Y_(a,b,c), taken from the largest b down.
     float2 acc[F::E];
 #pragma unroll
     for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
-    const int cnt = gt.count[g];
-    for (int s = cnt - 1; s >= 0; --s) {
+    const int jend = s_end[g];
+    for (; j < jend; ++j) {
+      float2 d[F::E];
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) d[e] = nd[e];
+      if (j + 1 < nmem) load_member<N, TK, EC>(X, a, s_grid[j + 1], zs, kt, tid0, nd);
       const int tid = col_hide<EC>(tid0);
       const int c = tid % TK, t = tid / TK;
       const int kx = kt * TK + c;
-      const int m = gt.grid[g][s];
-      const float2* __restrict__ src = X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * Kx + kx;
-      float2 d[F::E];
-#pragma unroll
-      for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * Kx];
-      F::run(d, t, tw, T, ColSlot<TK>{c});
-      const float fx = gt.coef[g][s] * ipow((float)kx * (2.0f / N), gt.a[g][s]);
+      F::run(d, t, twl, T, ColSlot<TK>{c});
+      const float fx = s_coef[j] * ipow((float)kx * (2.0f / N), s_pa[j]);
 #pragma unroll
       for (int e = 0; e < F::E; ++e) {
         const float ty = EC == 8 ? (float)signed_freq<N>(F::out_index(t, e)) * (2.0f / N) : tyv[e];
@@ -137,7 +166,7 @@ static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0, int 
   a.h_group_stride = (int64_t)p.H_group_stride;
   a.gt = at<const GroupTable>(ws, p.off_tables);
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
-  const size_t shmem = (size_t)TK * N * sizeof(float2);
+  const size_t shmem = (size_t)(TK + 1) * N * sizeof(float2);  // column tile + twiddles
   if (N >= 2048 || p.col_e[0] == 8) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
