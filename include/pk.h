@@ -193,7 +193,7 @@ pk_status pk_x_planes(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_
 /* Schedules of the column transforms (the FFTs along y and along z): the values each
  * thread holds, 16 (radices 16, 8, 4 at N = 512: fewer threads per transform) or 8
  * (radices 8, 8, 8: half the registers). A process-wide table keyed by (N, ell_max),
- * default 16 for both passes, read when a call plans its work (not thread-safe against
+ * default 16 for the y pass and 8 for the z pass, read when a call plans its work (not thread-safe against
  * concurrent changes). Both schedules compute the same transform; results agree to FP32
  * rounding. At N = 2048 only the 8-value schedule is built (16 values per thread would
  * need more than 256 registers): it is the only value reported and accepted there.

@@ -52,7 +52,9 @@ static int auto_slab(int N, int G, int Kx) {
 }
 
 // Schedules of the column transforms (values per thread of the y and z passes), per
-// (N, ell_max): set by pk_set_schedule or the autotuner; 0 = not set, meaning 16.
+// (N, ell_max): set by pk_set_schedule or the autotuner; 0 = not set, meaning 16 for the
+// y pass and 8 for the z pass (whose prefetched column does not fit the registers of the
+// 16-value schedule).
 struct Schedule {
   int y, z;
 };
@@ -126,7 +128,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.z_blocks = (int)(items < 512 ? items : 512);
   const Schedule sc = g_sched[log2_of(p.N)][p.ell_max / 2];
   p.col_e[0] = p.N >= 2048 ? 8 : (sc.y ? sc.y : 16);  // only the 8-value schedule is built at 2048
-  p.col_e[1] = p.N >= 2048 ? 8 : (sc.z ? sc.z : 16);
+  p.col_e[1] = p.N >= 2048 ? 8 : (sc.z ? sc.z : 8);
 
   // groups (n, c) and their members (grid index, a, b, multinomial weight)
   GroupTable& gt = p.groups;
@@ -438,7 +440,7 @@ pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t
   if (!y_values || !z_values) return fail(PK_EINVAL, "null output pointer");
   const Schedule sc = g_sched[log2_of(N)][ell_max / 2];
   *y_values = N >= 2048 ? 8 : (sc.y ? sc.y : 16);
-  *z_values = N >= 2048 ? 8 : (sc.z ? sc.z : 16);
+  *z_values = N >= 2048 ? 8 : (sc.z ? sc.z : 8);
   return PK_OK;
 }
 

@@ -213,27 +213,69 @@ __device__ __forceinline__ int isqrt_i(int n) {
   return s;
 }
 
-template <int N, int TK, int EC>
-__device__ __forceinline__ void zfft(const float2* __restrict__ col, int zstride, int c, int t0, const float2* tw,
-                                     float2* T, float2 (&d)[Fft<N, EC>::E]) {
+// Column (kx tile, ky) of the z pass: its H address (group 0), tile and row stride.
+struct ZItem {
+  const float2* base;
+  int kt, M, s, zstride;
+};
+
+template <int TK>
+__device__ __forceinline__ ZItem z_item(int64_t item, const float2* __restrict__ H, const int64_t* item0,
+                                        const int64_t* regoff, const int* Mt, int nkt, int c) {
+  int kt = 0, hi = nkt;  // the tile: the last kt with item0[kt] <= item
+  while (hi - kt > 1) {
+    const int mid = (kt + hi) >> 1;
+    if (item0[mid] <= item) kt = mid; else hi = mid;
+  }
+  ZItem z;
+  z.kt = kt;
+  z.M = Mt[kt];
+  z.s = (int)(item - item0[kt]);
+  z.zstride = (2 * z.M + 1) * TK;
+  z.base = H + regoff[kt] + (size_t)z.s * TK + c;
+  return z;
+}
+
+template <int N, int EC>
+__device__ __forceinline__ void z_load(const float2* __restrict__ col, int zstride, int t0,
+                                       float2 (&d)[Fft<N, EC>::E]) {
   using F = Fft<N, EC>;
   const int t = col_hide<EC>(t0);
 #pragma unroll
   for (int e = 0; e < F::E; ++e) d[e] = col[(size_t)F::in_index(t, e) * zstride];
-  F::run(d, t, tw, T, ColSlot<TK>{c});
 }
 
-// acc <- acc tz + FFT_z[H_(n, c)] for c = CMAX .. 0 (Horner in tz over the z-power groups
-// first .. first + CMAX of degree n).
-template <int N, int TK, int EC, int CMAX>
-__device__ __forceinline__ void z_horner(const float2* base, int64_t gstride, int first, int zstride, int c, int t,
-                                         const float2* tw, float2* T, float2 (&acc)[Fft<N, EC>::E]) {
+// z-power group taken at step k of a column: H_00 first, then each degree from the
+// highest power of z down (Horner in tz): (2,2) (2,1) (2,0) (4,4) .. (4,0) (6,6) .. (6,0).
+__host__ __device__ constexpr int zseq(int k) { return k == 0 ? 0 : (k <= 3 ? 4 - k : (k <= 8 ? 12 - k : 24 - k)); }
+
+// Step k: takes the prefetched column of group zseq(k) into d, starts loading the next
+// one (the next group of this column, or group 0 of the next column), then transforms d.
+template <int N, int TK, int EC, int NG>
+__device__ __forceinline__ void z_step(int k, float2 (&nd)[Fft<N, EC>::E], float2 (&d)[Fft<N, EC>::E],
+                                       const ZItem& cur, const ZItem& nxt, bool more, int64_t gstride, int c, int t,
+                                       const float2* twl, float2* T) {
+  using F = Fft<N, EC>;
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) d[e] = nd[e];
+  if (k + 1 < NG)
+    z_load<N, EC>(cur.base + (size_t)zseq(k + 1) * gstride, cur.zstride, t, nd);
+  else if (more)
+    z_load<N, EC>(nxt.base, nxt.zstride, t, nd);
+  F::run(d, col_hide<EC>(t), twl, T, ColSlot<TK>{c});
+}
+
+// acc <- acc tz + FFT_z[H_(n, c)] over steps k0 .. k0 + CMAX (c = CMAX .. 0).
+template <int N, int TK, int EC, int NG, int CMAX>
+__device__ __forceinline__ void z_horner(int k0, float2 (&nd)[Fft<N, EC>::E], float2 (&acc)[Fft<N, EC>::E],
+                                         const ZItem& cur, const ZItem& nxt, bool more, int64_t gstride, int c,
+                                         int t, const float2* twl, float2* T) {
   using F = Fft<N, EC>;
 #pragma unroll
   for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
-  auto step = [&](int cz) {
+  auto step = [&](int k) {
     float2 u[F::E];
-    zfft<N, TK, EC>(base + (size_t)(first + cz) * gstride, zstride, c, t, tw, T, u);
+    z_step<N, TK, EC, NG>(k, nd, u, cur, nxt, more, gstride, c, t, twl, T);
     const int tt = col_hide<EC>(t);
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -245,10 +287,17 @@ __device__ __forceinline__ void z_horner(const float2* base, int64_t gstride, in
   if constexpr (EC == 8) {
     // one transform at a time: unrolled, the loads of several would be hoisted together
 #pragma unroll 1
-    for (int cz = CMAX; cz >= 0; --cz) step(cz);
+    for (int k = k0; k <= k0 + CMAX; ++k) step(k);
   } else {
-    for (int cz = CMAX; cz >= 0; --cz) step(cz);
+    for (int k = k0; k <= k0 + CMAX; ++k) step(k);
   }
+}
+
+// Bytes of the z pass's LDS: the transform area, the twiddles, the FP64 bin sums, the
+// tile table and the per-axis window tables.
+__host__ __device__ constexpr size_t zpass_lds_bytes(int N, int TK, int nbins, int nkt) {
+  return (size_t)TK * N * 8 + (size_t)N * 8 + (size_t)nbins * kNumSums * 8 + (size_t)(2 * nkt + 1) * 8 +
+         (size_t)2 * N * 4 + (size_t)nkt * 4;
 }
 
 template <int N, int TK, int ELL, int EC>
@@ -259,40 +308,58 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
                                                                   const double* __restrict__ scal,
                                                                   double* __restrict__ zpart, const ZArgs a) {
   using F = Fft<N, EC>;
+  constexpr int NG = ELL == 0 ? 1 : (ELL == 2 ? 4 : (ELL == 4 ? 9 : 16));
+  // LDS: every table the loop reads, so that no wait inside it drains the prefetch of the
+  // next column (loads of global memory retire in order)
   extern __shared__ __align__(16) char smem[];
   float2* T = reinterpret_cast<float2*>(smem);
-  double* bins = reinterpret_cast<double*>(smem + (size_t)TK * N * sizeof(float2));
+  float2* twl = T + TK * N;
+  double* bins = reinterpret_cast<double*>(twl + N);
+  int64_t* item0 = reinterpret_cast<int64_t*>(bins + a.nbins * kNumSums);
+  int64_t* regoff = item0 + a.nkt + 1;
+  float* ivw = reinterpret_cast<float*>(regoff + a.nkt);
+  float* alw = ivw + N;
+  int* Mt = reinterpret_cast<int*>(alw + N);
   const int tid = threadIdx.x;
   const int c = tid % TK, t = tid / TK;
   for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) bins[i] = 0.0;
+  for (int i = tid; i < N; i += blockDim.x) {
+    twl[i] = tw[i];
+    ivw[i] = invw2[i];
+    alw[i] = alias[i];
+  }
+  for (int i = tid; i <= a.nkt; i += blockDim.x) item0[i] = a.tt->item0[i];
+  for (int i = tid; i < a.nkt; i += blockDim.x) {
+    regoff[i] = a.tt->regoff[i];
+    Mt[i] = a.tt->M[i];
+  }
   const double S = scal[kNoiseS];
   const float twoN = 2.0f / N;
+  __syncthreads();
   // consecutive items (neighbouring ky columns of one tile, which share lines when the
   // tile is narrower than 128 bytes) go to blocks of one XCD
-  const int64_t first = xcd_group(blockIdx.x, gridDim.x);
-  for (int64_t item = first; item < a.n_items; item += gridDim.x) {
-    int kt = 0, hi = a.nkt;  // the tile: the last kt with item0[kt] <= item
-    while (hi - kt > 1) {
-      const int mid = (kt + hi) >> 1;
-      if (a.tt->item0[mid] <= item) kt = mid; else hi = mid;
-    }
-    const int M = a.tt->M[kt];
-    const int s = (int)(item - a.tt->item0[kt]);
-    const int ky = s - M;
-    const int kx = kt * TK + c;
-    const int zstride = (2 * M + 1) * TK;
-    const float2* base = H + a.tt->regoff[kt] + (size_t)s * TK + c;
+  int64_t item = xcd_group(blockIdx.x, gridDim.x);
+  ZItem cur = z_item<TK>(item < a.n_items ? item : 0, H, item0, regoff, Mt, a.nkt, c);
+  float2 nd[F::E];
+  if (item < a.n_items) z_load<N, EC>(cur.base, cur.zstride, t, nd);
+  for (; item < a.n_items; item += gridDim.x) {
+    const int64_t nitem = item + gridDim.x;
+    const bool more = nitem < a.n_items;
+    const ZItem nxt = more ? z_item<TK>(nitem, H, item0, regoff, Mt, a.nkt, c) : cur;
+    const int M = cur.M;
+    const int ky = cur.s - M;
+    const int kx = cur.kt * TK + c;
     const float tx = (float)kx * twoN, ty = (float)ky * twoN;
-    const float wxy = invw2[kx] * invw2[ky & (N - 1)];
-    const float cxy = alias[kx] * alias[ky & (N - 1)];
+    const float wxy = ivw[kx] * ivw[ky & (N - 1)];
+    const float cxy = alw[kx] * alw[ky & (N - 1)];
     const int n2xy = kx * kx + ky * ky;
     const double mu = kx == 0 ? 1.0 : 2.0;
 
     float2 a0[F::E];
-    zfft<N, TK, EC>(base, zstride, c, t, tw, T, a0);
+    z_step<N, TK, EC, NG>(0, nd, a0, cur, nxt, more, a.h_group_stride, c, t, twl, T);
 
     float2 acc[F::E];
-    if (ELL >= 2) z_horner<N, TK, EC, 2>(base, a.h_group_stride, 1, zstride, c, t, tw, T, acc);
+    if (ELL >= 2) z_horner<N, TK, EC, NG, 2>(1, nd, acc, cur, nxt, more, a.h_group_stride, c, t, twl, T);
     {
       // pass 1: counts, |n|, Q0, Q2 (ell_max >= 2) and the noise
       const int tt = col_hide<EC>(t);
@@ -304,8 +371,8 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const bool valid = n2 > 0 && n2 < a.K2;
         const int b = valid ? isqrt_i(n2) / a.dn : 0;
         float iw = 1.0f, noise_f = 1.0f;
-        if (a.compensate >= 1) iw = wxy * invw2[kzi];
-        if (a.compensate == 2) noise_f = cxy * alias[kzi] * iw;
+        if (a.compensate >= 1) iw = wxy * ivw[kzi];
+        if (a.compensate == 2) noise_f = cxy * alw[kzi] * iw;
         const float2 z0 = a0[e];
         const float q0 = (z0.x * z0.x + z0.y * z0.y) * iw;
         double w4[4];
@@ -326,7 +393,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
       }
     }
     if (ELL >= 4) {
-      z_horner<N, TK, EC, 4>(base, a.h_group_stride, 4, zstride, c, t, tw, T, acc);
+      z_horner<N, TK, EC, NG, 4>(4, nd, acc, cur, nxt, more, a.h_group_stride, c, t, twl, T);
       const int tt = col_hide<EC>(t);
 #pragma unroll
       for (int e = 0; e < F::E; ++e) {
@@ -335,7 +402,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const int n2 = n2xy + kz * kz;
         const bool valid = n2 > 0 && n2 < a.K2;
         const int b = valid ? isqrt_i(n2) / a.dn : 0;
-        const float iw = a.compensate >= 1 ? wxy * invw2[kzi] : 1.0f;
+        const float iw = a.compensate >= 1 ? wxy * ivw[kzi] : 1.0f;
         const float tz = (float)kz * twoN;
         const float t2 = tx * tx + ty * ty + tz * tz;
         const float inv_t4 = 1.0f / (t2 * t2);
@@ -347,7 +414,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
     }
     if (ELL >= 6) {
       // A_6 = |t|^-6 sum_c tz^c FFT_z[H_(6,c)], groups 9 .. 15
-      z_horner<N, TK, EC, 6>(base, a.h_group_stride, 9, zstride, c, t, tw, T, acc);
+      z_horner<N, TK, EC, NG, 6>(9, nd, acc, cur, nxt, more, a.h_group_stride, c, t, twl, T);
       const int tt = col_hide<EC>(t);
 #pragma unroll
       for (int e = 0; e < F::E; ++e) {
@@ -356,7 +423,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const int n2 = n2xy + kz * kz;
         const bool valid = n2 > 0 && n2 < a.K2;
         const int b = valid ? isqrt_i(n2) / a.dn : 0;
-        const float iw = a.compensate >= 1 ? wxy * invw2[kzi] : 1.0f;
+        const float iw = a.compensate >= 1 ? wxy * ivw[kzi] : 1.0f;
         const float tz = (float)kz * twoN;
         const float t2 = tx * tx + ty * ty + tz * tz;
         const float inv_t6 = 1.0f / (t2 * t2 * t2);
@@ -366,6 +433,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         bin_add<1>(bins, b, valid, w, 6);
       }
     }
+    cur = nxt;
   }
   __syncthreads();
   double* out = zpart + (size_t)blockIdx.x * a.nbins * kNumSums;
@@ -374,7 +442,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
 
 template <int N, int TK, int ELL, int EC>
 static hipError_t launch_z4(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
-  const size_t shmem = (size_t)TK * N * sizeof(float2) + (size_t)p.nbins * kNumSums * sizeof(double);
+  const size_t shmem = zpass_lds_bytes(N, TK, p.nbins, p.nkt);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL, EC>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   hipLaunchKernelGGL((zpass_kernel<N, TK, ELL, EC>), dim3(p.z_blocks), dim3(TK * Fft<N, EC>::T), shmem, s,

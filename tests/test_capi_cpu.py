@@ -107,13 +107,13 @@ def test_slab_plans():
 
 def test_schedule_table():
     """The column-transform schedule table: defaults, round trip and rejected values."""
-    assert native.get_schedule(512, 4) == (16, 16)
+    assert native.get_schedule(512, 4) == (16, 8)   # defaults: 16 for y, 8 for z
     native.set_schedule(256, 2, 8, 16)
     try:
         assert native.get_schedule(256, 2) == (8, 16)
-        assert native.get_schedule(256, 4) == (16, 16)   # keyed by (N, ell_max)
+        assert native.get_schedule(256, 4) == (16, 8)   # keyed by (N, ell_max)
     finally:
-        native.set_schedule(256, 2, 16, 16)
+        native.set_schedule(256, 2, 16, 8)
     assert native.get_schedule(2048, 4) == (8, 8)   # the only schedule built at 2048
     native.set_schedule(2048, 4, 8, 8)
     for bad in [(500, 4, 16, 16), (512, 3, 16, 16), (512, 4, 12, 16), (512, 4, 16, 4), (2048, 4, 16, 8)]:

@@ -325,7 +325,7 @@ def test_every_schedule_matches_oracle(pk, N):
         assert native.get_schedule(N, cfg["ell_max"]) == best
         compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
     finally:
-        native.set_schedule(N, cfg["ell_max"], 16, 16)
+        native.set_schedule(N, cfg["ell_max"], 16, 8)   # back to the defaults
 
 
 @pytest.mark.parametrize("N,assign,xs", [(32, 2, 1), (32, 3, 4), (64, 3, 8), (64, 2, 32)])
@@ -371,7 +371,7 @@ def test_slabs_match_oracle(pk, N, assign, xs):
             assert best[0] in (8, 16) and best[1] in (8, 16)
             compare(pk.pk_multipoles(g, r, scfg), ref, cfg)
         finally:
-            native.set_schedule(N, cfg["ell_max"], 16, 16)
+            native.set_schedule(N, cfg["ell_max"], 16, 8)   # back to the defaults
 
 
 # ------------------------------------------------------------------------- degenerate inputs
