@@ -266,8 +266,8 @@ __device__ __forceinline__ uint32_t block_scan_lds(uint32_t* a, int n) {
 // threads store consecutive slots of one bucket (runs of ~tile/buckets particles)
 // instead of scattering 16-byte stores over all buckets, which costs a partial-line
 // write per particle.
-constexpr int kSortThreads = 512;
-constexpr int kSortTile = 2048;
+constexpr int kSortThreads = 1024;
+constexpr int kSortTile = 4096;
 constexpr int kSortPer = kSortTile / kSortThreads;
 
 // LDS of one staged scatter: cur, tcnt, gb (uint32[nb] each), stage float4[tile],
