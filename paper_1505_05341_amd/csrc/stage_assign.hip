@@ -97,13 +97,9 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
   __syncthreads();
 }
 
-// One-visit gather (see gather_rows) at N = 1024, where it pays for its S x registers.
-template <int N>
-constexpr bool xpass_one_visit() { return N == 1024; }
-
 // Gathers the NG kept monomial rows of the block's target row into LDS rows[g][x]
 // (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
-template <int N, int ASSIGN, int NG, int NP, bool OV, int S = (ASSIGN == PK_CIC ? 2 : 3)>
+template <int N, int ASSIGN, int NG, int NP, int S = (ASSIGN == PK_CIC ? 2 : 3)>
 __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict__ sorted, const uint32_t (&beg)[S * S],
                                             const uint32_t (&pre)[S * S + 1], const XArgs& a) {
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
@@ -118,19 +114,15 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   uint32_t* st = cnt + N;
   const int tid = threadIdx.x;
   // FP32 register sums; the order in which a cell's particles arrive is set by atomics
-  // in the sorts, so repeated runs differ at the FP32 rounding level of a cell
-  // OV (one visit): each thread owns base cells and adds each particle once to the S target
-  // cells of its stencil, keeping one set of sums per stencil offset (S x more registers,
-  // S x fewer particle visits); otherwise each thread owns target cells and gathers from
-  // the S base cells that reach it.
-  constexpr int NS = OV ? S : 1;
-  float acc[CPT][NS][NG];
+  // in the sorts, so repeated runs differ at the FP32 rounding level of a cell. Each
+  // thread owns target cells and gathers from the S base cells that reach them. (Adding
+  // each particle once to the S cells of its stencil, with S sets of sums, was measured
+  // slower at every size once the sums fit 64 registers: it costs the second block per CU.)
+  float acc[CPT][NG];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int o = 0; o < NS; ++o)
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc[c][o][g] = 0.0f;
+    for (int g = 0; g < NG; ++g) acc[c][g] = 0.0f;
   for (int i = tid; i < N; i += NT) cnt[i] = 0u;
   __syncthreads();
   const uint32_t total = pre[S * S];
@@ -195,37 +187,19 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     for (int c = 0; c < CPT; ++c) {
       const int x = tid + c * NT;
       if (x < N) {
-        if (OV) {
-          // each particle of base cell x, once: stencil offset o reaches cell x + O0 + o
-          const uint32_t k1 = st[x + 1];
-          for (uint32_t k = st[x]; k < k1; ++k) {
+        // target cell x receives from base cells x - O0 - o with stencil offset O0 + o
+#pragma unroll
+        for (int o = 0; o < S; ++o) {
+          const int sc = (x - O0 - o) & (N - 1);
+          const uint32_t k1 = st[sc + 1];
+          for (uint32_t k = st[sc]; k < k1; ++k) {
             const int i = perm[k];
             const float4 p = pa[i];
-            float wo[S];
-#pragma unroll
-            for (int o = 0; o < S; ++o) wo[o] = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
+            const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
             float m[NG];
             kept_monomials<NG>(p.z, p.w, pr[i], m);
 #pragma unroll
-            for (int g = 0; g < NG; ++g)
-#pragma unroll
-              for (int o = 0; o < NS; ++o) acc[c][o][g] += wo[o] * m[g];
-          }
-        } else {
-          // target cell x receives from base cells x - O0 - o with stencil offset O0 + o
-#pragma unroll
-          for (int o = 0; o < S; ++o) {
-            const int sc = (x - O0 - o) & (N - 1);
-            const uint32_t k1 = st[sc + 1];
-            for (uint32_t k = st[sc]; k < k1; ++k) {
-              const int i = perm[k];
-              const float4 p = pa[i];
-              const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
-              float m[NG];
-              kept_monomials<NG>(p.z, p.w, pr[i], m);
-#pragma unroll
-              for (int g = 0; g < NG; ++g) acc[c][0][g] += w * m[g];
-            }
+            for (int g = 0; g < NG; ++g) acc[c][g] += w * m[g];
           }
         }
         cnt[x] = 0u;  // ready for the next chunk (only this thread touches cell x here)
@@ -233,34 +207,15 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     }
     __syncthreads();
   }
-  // rows alias the gather area (all gathers are done: barrier above). With OV the sums of
-  // the own cell (offset -O0) are stored first and each other offset is added in a phase
-  // of its own, so every cell has a single writer in each phase.
-  constexpr int OWN = OV ? -O0 : 0;
+  // rows alias the gather area (all gathers are done: barrier above)
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int x = tid + c * NT;
     if (x < N) {
 #pragma unroll
-      for (int g = 0; g < NG; ++g) lds[g * N + x] = acc[c][OWN][g];
+      for (int g = 0; g < NG; ++g) lds[g * N + x] = acc[c][g];
 #pragma unroll
       for (int g = NG; g < 2 * NP; ++g) lds[g * N + x] = 0.0f;
-    }
-  }
-  if (OV) {
-#pragma unroll
-    for (int o = 0; o < NS; ++o) {
-      if (o == OWN) continue;
-      __syncthreads();
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int x = tid + c * NT;
-        if (x < N) {
-          const int xt = (x + O0 + o) & (N - 1);
-#pragma unroll
-          for (int g = 0; g < NG; ++g) lds[g * N + xt] += acc[c][o][g];
-        }
-      }
     }
   }
   __syncthreads();
@@ -272,12 +227,13 @@ struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
 
-// Waves per SIMD the registers are budgeted for: 8 (4 blocks of 512 threads per CU, which
-// the 32 KB of LDS of the 15 gathered rows allow; <= 64 VGPRs, measured 11% faster than 6)
-// up to N = 512, 4 (one block of 1024 threads) from 1024 on; 4 for the 28 gathered rows of
-// ell_max = 6 at every N.
+// Waves per SIMD the registers are budgeted for (<= 64 VGPRs at 8): 8 up to N = 1024, i.e.
+// 4 blocks of 512 threads per CU (up to 512) or 2 of 1024 threads (at 1024), as the LDS
+// of the 15 gathered rows allows (measured 11% faster than 6 at 512, 14-30% than 4 at
+// 1024); 4 at 2048, where the rows take 128 KB of LDS (one block per CU), and for the 28
+// gathered rows of ell_max = 6.
 template <int N, int ELL>
-constexpr int xpass_waves() { return (N >= 1024 || ELL >= 6) ? 4 : 8; }
+constexpr int xpass_waves() { return (N >= 2048 || ELL >= 6) ? 4 : 8; }
 
 // x-transformed value at kx of kept row j, from the packed spectra in LDS: rows (2q, 2q+1)
 // were transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
@@ -321,7 +277,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     const uint32_t end = rowoff[r + 1];
     pre[s + 1] = pre[s] + (end > beg[s] ? end - beg[s] : 0u);  // offsets are non-decreasing
   }
-  gather_rows<N, ASSIGN, GK, NP, xpass_one_visit<N>()>(lds, sorted, beg, pre, a);
+  gather_rows<N, ASSIGN, GK, NP>(lds, sorted, beg, pre, a);
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
   const int q = tid / F::T, t = tid % F::T;
