@@ -1,8 +1,8 @@
 // LOS-weighted mass assignment fused with the FFT along x (Sec. 3, Eqs. 11 and 13;
 // Sec. 4 for the assignment).
 //
-// One block owns one target grid row (y, z) of the 1, 7 or 22 monomial grids F rhat^m.
-// Only the 1, 6 or 15 monomials with a power of rhat_z below 2 are gathered and
+// One block owns one target grid row (y, z) of the 1, 7, 22 or 50 monomial grids
+// F rhat^m. Only the 1, 6, 15 or 28 monomials with a power of rhat_z below 2 are gathered and
 // transformed; the others follow exactly from rhat_x^2 + rhat_y^2 + rhat_z^2 = 1 and are
 // written as combinations of the transformed rows (basis.hpp). The particles whose
 // stencil reaches the row are those of a few source rows, which the counting sort made
@@ -38,9 +38,6 @@ struct XArgs {
   int pbase;            // plane of X that receives plane z0
   int64_t grid_stride;  // float2 elements per grid of X: xr * xs * N * Kx
 };
-
-
-
 
 // Block geometry: 512 threads and chunks of 1024 particles up to N = 512; from N = 1024 on,
 // blocks of 1024 threads (one cell per thread at 1024, two at 2048) and chunks of 2048.
