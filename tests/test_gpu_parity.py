@@ -142,18 +142,30 @@ def test_xgrid_rows_match_oracle(pk):
             assert err < 1e-5, (m, iy, iz, err)
 
 
-@pytest.mark.parametrize("N,assign,los,kind", [(32, 2, 0, "tiny"), (64, 3, 0, "clustered"), (32, 2, 1, "tiny"),
-                                               (64, 2, 0, "clustered")])
-def test_ell6_matches_oracle(pk, N, assign, los, kind):
+@pytest.mark.parametrize("N,assign,los,kind,xs", [(32, 2, 0, "tiny", 0), (64, 3, 0, "clustered", 0),
+                                                  (32, 2, 1, "tiny", 0), (64, 2, 0, "clustered", 0),
+                                                  (64, 3, 0, "clustered", 8)])
+def test_ell6_matches_oracle(pk, N, assign, los, kind, xs):
     """ell_max = 6: 50 monomial grids (28 gathered, 22 from the identity), 16 z-power
-    groups, P6 from L_6; the whole estimator against the oracle."""
+    groups, P6 from L_6; the whole estimator against the oracle (also in slabs of 8
+    planes, and inside a batch next to an ell_max = 4 mock)."""
     if kind == "tiny":
         gal, ran, cfg = catalogs.tiny_plain(N=N, assign=assign, los=los, ell_max=6)
     else:
         gal, ran, cfg = catalogs.small_clustered(N=N, nbar=3e-4, ran_factor=10.0, assign=assign, los=los, ell_max=6)
-    got, ref = run_both(pk, gal, ran, cfg)
+    gcfg = dict(cfg, x_planes=xs) if xs else cfg
+    got, ref = run_both(pk, gal, ran, gcfg)
     assert "P6" in got
     compare(got, ref, cfg)
+    if kind == "clustered" and assign == 3:
+        g = pk.DeviceCatalog.from_host(gal)
+        r = pk.DeviceCatalog.from_host(ran)
+        c4 = dict(cfg, ell_max=4)
+        res, st = pk.pk_multipoles_batch([g, g, g], [r, r, r], [gcfg, c4, gcfg], lanes=2)
+        assert st == [0, 0, 0] and "P6" in res[0] and "P6" not in res[1]
+        compare(res[0], ref, cfg)
+        compare(res[2], ref, cfg)
+        np.testing.assert_array_equal(res[1]["nmodes"], ref.nmodes)
 
 
 def test_ell6_xgrid_rows(pk):
