@@ -232,17 +232,6 @@ struct XSwizzle {
 template <int N, int ELL>
 constexpr int xpass_waves() { return (N >= 2048 || ELL >= 6) ? 4 : 8; }
 
-// x-transformed value at kx of kept row j, from the packed spectra in LDS: rows (2q, 2q+1)
-// were transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
-// X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
-template <int N>
-__device__ __forceinline__ float2 kept_spectrum(const float2* T, int j, int kx) {
-  const float2 zk = T[(j >> 1) * N + XSwizzle()(kx)];
-  const float2 zm = T[(j >> 1) * N + XSwizzle()((N - kx) & (N - 1))];
-  return (j & 1) ? make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x))
-                 : make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-}
-
 template <int N, int ASSIGN, int ELL>
 __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
@@ -272,7 +261,9 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     const int64_t r = (int64_t)sz * N + sy;
     beg[s] = rowoff[r];
     const uint32_t end = rowoff[r + 1];
-    pre[s + 1] = pre[s] + (end > beg[s] ? end - beg[s] : 0u);  // offsets are non-decreasing
+    // offsets are non-decreasing; the sums are block-uniform and kept in scalar registers
+    // (the clamped difference is a vector instruction, which would hold S * S VGPRs)
+    pre[s + 1] = __builtin_amdgcn_readfirstlane(pre[s] + (end > beg[s] ? end - beg[s] : 0u));
   }
   gather_rows<N, ASSIGN, GK, NP>(lds, sorted, beg, pre, a);
 
@@ -298,25 +289,34 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     for (int e = 0; e < F::E; ++e) Tq[XSwizzle()(F::out_index(t, e))] = d[e];
   }
   __syncthreads();
+  // Thread kx < Kx (Kx <= N / 2 <= block size) unpacks the kept spectra at kx into
+  // registers once, stores them at their monomial index and forms the rows with a power
+  // of rhat_z of 2 or more from them by the identity of basis.hpp. Rows (2q, 2q+1) were
+  // transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
+  // X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
   const int Kx = a.Kx;
-  const size_t row = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx;
-  // kept rows, at their monomial index
-  for (int e = tid; e < GK * Kx; e += blockDim.x) {
-    const int j = e / Kx, kx = e - j * Kx;
-    X[(size_t)kept_monomial(j) * a.grid_stride + row + kx] = kept_spectrum<N>(T, j, kx);
-  }
-  // the rows with a power of rhat_z of 2 or more, from the identity of basis.hpp
+  if (tid < Kx) {
+    const int kx = tid;
+    const size_t o = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx + kx;
+    const int ik = XSwizzle()(kx), im = XSwizzle()((N - kx) & (N - 1));
+    float2 xk[2 * NP];
 #pragma unroll
-  for (int dd = 0; dd < ND; ++dd) {
-    for (int kx = tid; kx < Kx; kx += blockDim.x) {
+    for (int qq = 0; qq < NP; ++qq) {
+      const float2 zk = T[qq * N + ik], zm = T[qq * N + im];
+      xk[2 * qq] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      xk[2 * qq + 1] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+    }
+#pragma unroll
+    for (int j = 0; j < GK; ++j) X[(size_t)kept_monomial(j) * a.grid_stride + o] = xk[j];
+#pragma unroll
+    for (int dd = 0; dd < ND; ++dd) {
       float2 v = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int u = 0; u < dep_terms(dd); ++u) {
-        const float2 xj = kept_spectrum<N>(T, dep_kept(dd, u), kx);
-        v.x += dep_coef(dd, u) * xj.x;
-        v.y += dep_coef(dd, u) * xj.y;
+        v.x += dep_coef(dd, u) * xk[dep_kept(dd, u)].x;
+        v.y += dep_coef(dd, u) * xk[dep_kept(dd, u)].y;
       }
-      X[(size_t)dep_monomial(dd) * a.grid_stride + row + kx] = v;
+      X[(size_t)dep_monomial(dd) * a.grid_stride + o] = v;
     }
   }
 }
