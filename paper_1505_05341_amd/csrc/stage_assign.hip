@@ -94,6 +94,25 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
   __syncthreads();
 }
 
+// Adds a chunk particle (pa = (f, w W_y W_z, rx, ry), rz) with stencil offset o along x to
+// the NG kept-monomial sums of a target cell: CIC weights (1 - f, f) for o = (0, 1); TSC
+// 3/4 - d^2 for o = 0 and (1/2 + o d)^2 / 2 for o = +-1.
+template <int NG, int ASSIGN>
+__device__ __forceinline__ void add_particle(float (&acc)[NG], const float4 p, const float rz, const int o) {
+  float wx;
+  if (ASSIGN == PK_CIC) {
+    wx = o != 0 ? p.x : 1.0f - p.x;
+  } else {
+    const float h = 0.5f + (float)o * p.x;
+    wx = o == 0 ? 0.75f - p.x * p.x : 0.5f * h * h;
+  }
+  const float w = p.y * wx;
+  float m[NG];
+  kept_monomials<NG>(p.z, p.w, rz, m);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) acc[g] += w * m[g];
+}
+
 // Gathers the NG kept monomial rows of the block's target row into LDS rows[g][x]
 // (rows NG .. 2*NP-1 are zeroed). S*S source rows: particles beg[s] .. beg[s] + len.
 template <int N, int ASSIGN, int NG, int NP, int S = (ASSIGN == PK_CIC ? 2 : 3)>
@@ -126,7 +145,11 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   for (uint32_t c0 = 0; c0 < total; c0 += XCHUNK) {
     const int n = (int)(total - c0 < (uint32_t)XCHUNK ? total - c0 : (uint32_t)XCHUNK);
     // 1. per-particle values: all of this thread's loads are issued first
+    // defined on every path: a value left undefined for the threads past the chunk end
+    // can be kept in its register across iterations, which costs registers
     float4 qv[XPER];
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) qv[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     int sv[XPER];
 #pragma unroll
     for (int j = 0; j < XPER; ++j) {
@@ -184,19 +207,27 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     for (int c = 0; c < CPT; ++c) {
       const int x = tid + c * NT;
       if (x < N) {
-        // target cell x receives from base cells x - O0 - o with stencil offset O0 + o
-#pragma unroll
-        for (int o = 0; o < S; ++o) {
-          const int sc = (x - O0 - o) & (N - 1);
-          const uint32_t k1 = st[sc + 1];
-          for (uint32_t k = st[sc]; k < k1; ++k) {
+        // Target cell x receives from the base cells x - 1 ... x - O0 (stencil offset
+        // o = x - base, 1 down to O0). Their particles are adjacent in perm (sorted by
+        // base cell), so one loop walks them all and takes o from the cell boundaries:
+        // the lanes of a wave then wait for the largest sum of S counts rather than for
+        // the largest count S times. The periodic neighbours of x = 0 (cell N - 1) and,
+        // for TSC, of x = N - 1 (cell 0) follow in a loop of their own.
+        const uint32_t sx = st[x];
+        const uint32_t sx1 = st[x + 1];
+        const uint32_t kb = st[x > 0 ? x - 1 : 0];
+        const uint32_t ke = ASSIGN == PK_CIC ? sx1 : st[x + 2 < N ? x + 2 : N];
+        for (uint32_t k = kb; k < ke; ++k) {
+          const int i = perm[k];
+          const int o = ASSIGN == PK_CIC ? (int)(k < sx) : (int)(k < sx) - (int)(k >= sx1);
+          add_particle<NG, ASSIGN>(acc[c], pa[i], pr[i], o);
+        }
+        const bool wrap_lo = x == 0, wrap_hi = ASSIGN != PK_CIC && x == N - 1;
+        if (wrap_lo || wrap_hi) {
+          const uint32_t k1 = wrap_lo ? st[N] : st[1];
+          for (uint32_t k = wrap_lo ? st[N - 1] : st[0]; k < k1; ++k) {
             const int i = perm[k];
-            const float4 p = pa[i];
-            const float w = p.y * stencil_weight<ASSIGN>(p.x, O0 + o);
-            float m[NG];
-            kept_monomials<NG>(p.z, p.w, pr[i], m);
-#pragma unroll
-            for (int g = 0; g < NG; ++g) acc[c][g] += w * m[g];
+            add_particle<NG, ASSIGN>(acc[c], pa[i], pr[i], wrap_lo ? 1 : -1);
           }
         }
         cnt[x] = 0u;  // ready for the next chunk (only this thread touches cell x here)
@@ -271,7 +302,9 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   const int q = tid / F::T, t = tid % F::T;
   const bool active = q < NP;
   float2* T = reinterpret_cast<float2*>(lds);  // pair q uses T[q N, (q + 1) N), its two rows
-  float2 d[F::E];
+  float2 d[F::E];  // zero for the inactive threads (defined on every path)
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) d[e] = make_float2(0.0f, 0.0f);
   if (active) {
     const float* r0 = lds + 2 * q * N;
     const float* r1 = r0 + N;
@@ -306,8 +339,12 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
       xk[2 * qq] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       xk[2 * qq + 1] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
     }
+    // the grid stride is opaque here: otherwise the compiler forms all GK + ND products
+    // with it up front and holds them in (spilled) scalar registers through the kernel
+    int64_t gs = a.grid_stride;
+    asm volatile("" : "+s"(gs));
 #pragma unroll
-    for (int j = 0; j < GK; ++j) X[(size_t)kept_monomial(j) * a.grid_stride + o] = xk[j];
+    for (int j = 0; j < GK; ++j) X[(size_t)kept_monomial(j) * gs + o] = xk[j];
 #pragma unroll
     for (int dd = 0; dd < ND; ++dd) {
       float2 v = make_float2(0.0f, 0.0f);
@@ -316,7 +353,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
         v.x += dep_coef(dd, u) * xk[dep_kept(dd, u)].x;
         v.y += dep_coef(dd, u) * xk[dep_kept(dd, u)].y;
       }
-      X[(size_t)dep_monomial(dd) * a.grid_stride + o] = v;
+      X[(size_t)dep_monomial(dd) * gs + o] = v;
     }
   }
 }
