@@ -322,9 +322,9 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     for (int e = 0; e < F::E; ++e) Tq[XSwizzle()(F::out_index(t, e))] = d[e];
   }
   __syncthreads();
-  // Thread kx < Kx (Kx <= N / 2 <= block size) unpacks the kept spectra at kx into
-  // registers once, stores them at their monomial index and forms the rows with a power
-  // of rhat_z of 2 or more from them by the identity of basis.hpp. Rows (2q, 2q+1) were
+  // Thread kx < Kx (Kx <= N / 2 <= block size) unpacks each kept spectrum at kx once,
+  // stores it at its monomial index and adds it into the rows with a power of rhat_z of 2
+  // or more, which the identity of basis.hpp makes from the kept ones. Rows (2q, 2q+1) were
   // transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
   // X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
   const int Kx = a.Kx;
@@ -332,29 +332,38 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     const int kx = tid;
     const size_t o = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx + kx;
     const int ik = XSwizzle()(kx), im = XSwizzle()((N - kx) & (N - 1));
-    float2 xk[2 * NP];
-#pragma unroll
-    for (int qq = 0; qq < NP; ++qq) {
-      const float2 zk = T[qq * N + ik], zm = T[qq * N + im];
-      xk[2 * qq] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-      xk[2 * qq + 1] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-    }
     // the grid stride is opaque here: otherwise the compiler forms all GK + ND products
     // with it up front and holds them in (spilled) scalar registers through the kernel
     int64_t gs = a.grid_stride;
     asm volatile("" : "+s"(gs));
+    // one row pair at a time: its two kept rows are stored and added into the sums of
+    // the dependent rows, so only those ND sums stay live (not all GK kept values)
+    float2 v[ND > 0 ? ND : 1];
 #pragma unroll
-    for (int j = 0; j < GK; ++j) X[(size_t)kept_monomial(j) * gs + o] = xk[j];
+    for (int dd = 0; dd < ND; ++dd) v[dd] = make_float2(0.0f, 0.0f);
 #pragma unroll
-    for (int dd = 0; dd < ND; ++dd) {
-      float2 v = make_float2(0.0f, 0.0f);
+    for (int qq = 0; qq < NP; ++qq) {
+      const float2 zk = T[qq * N + ik], zm = T[qq * N + im];
+      const float2 xp[2] = {make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)),
+                            make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x))};
 #pragma unroll
-      for (int u = 0; u < dep_terms(dd); ++u) {
-        v.x += dep_coef(dd, u) * xk[dep_kept(dd, u)].x;
-        v.y += dep_coef(dd, u) * xk[dep_kept(dd, u)].y;
+      for (int h = 0; h < 2; ++h) {
+        const int j = 2 * qq + h;
+        if (j < GK) {
+          X[(size_t)kept_monomial(j) * gs + o] = xp[h];
+#pragma unroll
+          for (int dd = 0; dd < ND; ++dd)
+#pragma unroll
+            for (int u = 0; u < dep_terms(dd); ++u)
+              if (dep_kept(dd, u) == j) {
+                v[dd].x += dep_coef(dd, u) * xp[h].x;
+                v[dd].y += dep_coef(dd, u) * xp[h].y;
+              }
+        }
       }
-      X[(size_t)dep_monomial(dd) * gs + o] = v;
     }
+#pragma unroll
+    for (int dd = 0; dd < ND; ++dd) X[(size_t)dep_monomial(dd) * gs + o] = v[dd];
   }
 }
 
