@@ -263,6 +263,15 @@ struct XSwizzle {
 template <int N, int ELL>
 constexpr int xpass_waves() { return (N >= 2048 || ELL >= 6) ? 4 : 8; }
 
+// Bytes before the x pass's LDS twiddle table: the larger of the gather area and the
+// 2 NP transformed rows (which alias each other).
+template <int N, int NP>
+constexpr size_t xpass_tw_offset() {
+  const size_t rows = (size_t)2 * NP * N * sizeof(float);
+  const size_t g = gather_lds_bytes<N>();
+  return ((rows > g ? rows : g) + 15) / 16 * 16;
+}
+
 template <int N, int ASSIGN, int ELL>
 __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
@@ -296,6 +305,9 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     // (the clamped difference is a vector instruction, which would hold S * S VGPRs)
     pre[s + 1] = __builtin_amdgcn_readfirstlane(pre[s] + (end > beg[s] ? end - beg[s] : 0u));
   }
+  // the twiddles of the x transform in LDS (the barriers of the gather make them visible)
+  float2* twl = reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + xpass_tw_offset<N, NP>());
+  for (int i = tid; i < N; i += XGeom<N>::NT) twl[i] = tw[i];
   gather_rows<N, ASSIGN, GK, NP>(lds, sorted, beg, pre, a);
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
@@ -315,7 +327,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     }
   }
   float2* Tq = T + (active ? q * N : 0);
-  F::run(d, t, tw, Tq, XSwizzle(), active);
+  F::run(d, t, twl, Tq, XSwizzle(), active);
   __syncthreads();
   if (active) {
 #pragma unroll
@@ -371,7 +383,8 @@ template <int N, int ASSIGN, int ELL>
 static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t s) {
   constexpr int NP = (kept_count(ELL) + 1) / 2;
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
-  const size_t shmem = rows > gather_lds_bytes<N>() ? rows : gather_lds_bytes<N>();
+  (void)rows;
+  const size_t shmem = xpass_tw_offset<N, NP>() + (size_t)N * sizeof(float2);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL>), dim3(N, p.xs), dim3(XGeom<N>::NT), shmem, s,
