@@ -340,7 +340,9 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
   // tile is narrower than 128 bytes) go to blocks of one XCD
   int64_t item = xcd_group(blockIdx.x, gridDim.x);
   ZItem cur = z_item<TK>(item < a.n_items ? item : 0, H, item0, regoff, Mt, a.nkt, c);
-  float2 nd[F::E];
+  float2 nd[F::E];  // defined on every path (an undefined value can pin its register)
+#pragma unroll
+  for (int e = 0; e < F::E; ++e) nd[e] = make_float2(0.0f, 0.0f);
   if (item < a.n_items) z_load<N, EC>(cur.base, cur.zstride, t, nd);
   for (; item < a.n_items; item += gridDim.x) {
     const int64_t nitem = item + gridDim.x;
