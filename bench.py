@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of this
-# workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+# HBM traffic of the dominant kernel per launch, keyed by (workload, kernel) and reported
+# for that workload only, from two rocprofv3 --pmc runs of it (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the same
 # counter reads for a plain copy of known size (--copy-calibration: FETCH_SIZE reads 0.50
 # of the bytes read, WRITE_SIZE 1.00 of the bytes written). Valid only for the kernel
 # source it was measured on: the sha256 of the files listed is checked at run time and
@@ -36,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = ["paper_1505_05341_amd/csrc/" + f for f in
                  ("stage_assign.hip", "particle.hpp", "fft_dev.hpp", "plan.hpp", "dft_consts.h", "basis.hpp")]
 TRAFFIC = {
-    "assign_x": {"sha256": "aaf60233a9cce404b8053435d642b2610fdb754193cf935b8da12ed2b7719503",
+    ("clustered_512", "assign_x"): {"sha256": "aaf60233a9cce404b8053435d642b2610fdb754193cf935b8da12ed2b7719503",
                  "fetch_kib": 1584261.1, "write_kib": 11534336.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
@@ -50,8 +51,8 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    t = TRAFFIC.get(kernel)
+def measured_traffic(workload, kernel):
+    t = TRAFFIC.get((workload, kernel))
     if not t or t["sha256"] is None or t["sha256"] != source_digest(TRAFFIC_FILES):
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
@@ -394,7 +395,7 @@ def main():
                    "nbins": cfg["nbins"], "dn": cfg["dn"], "x_planes": xs,
                    "fft_schedule": {"y_values_per_thread": schedule[0], "z_values_per_thread": schedule[1]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if slabs else measured_traffic(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if slabs else measured_traffic(args.workload, dom),
                      "kernel": dom + (" + fft_y (slabs)" if slabs else ""),
                      "kernel_ms": stage_ms[dom], "algorithmic_bytes": byts[dom]},
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},

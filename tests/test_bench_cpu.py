@@ -32,3 +32,14 @@ def test_byte_model_matches_the_library_workspace():
     # slabs: the x and y transforms are timed as one stage
     s = bench.plan_bytes(dict(N=2048, box_min=(0, 0, 0), L=1.0, dn=2, nbins=512, ell_max=4), 10, 10, slabs=True)
     assert "fft_y" not in s and s["assign_x"] > s["fft_z_bin"]
+
+
+def test_traffic_is_reported_only_for_the_workload_it_was_measured_on():
+    """The calibrated HBM traffic in the bench line belongs to one (workload, kernel) pair:
+    another workload with the same dominant kernel reports null, not that figure."""
+    keys = list(bench.TRAFFIC)
+    assert keys and all(isinstance(k, tuple) and len(k) == 2 for k in keys)
+    for workload, kernel in keys:
+        for other in ("desi_1024", "survey", "tiny_32", "clustered_512"):
+            if other != workload:
+                assert bench.measured_traffic(other, kernel) is None
