@@ -181,7 +181,9 @@ pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_
 /* Where pk_stage_xgrids leaves grid `m`: complex64 values X[z][y][kx] for z < x_planes
  * (pk_x_planes), y < N, kx < kx_count: the x-transformed (unnormalised,
  * e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at byte `offset` of the
- * workspace. Monomial m has exponents (a, b, c) of rhat_x, rhat_y, rhat_z as returned by
+ * workspace. At N = 2048 the values are stored tile-major, X[z][kx / 4][y][kx % 4]
+ * (4-column tiles, so that the y transform reads each tile as one contiguous run).
+ * Monomial m has exponents (a, b, c) of rhat_x, rhat_y, rhat_z as returned by
  * pk_monomial. */
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
                           size_t* offset, int32_t* kx_count);

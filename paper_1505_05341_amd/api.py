@@ -159,13 +159,16 @@ def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: W
 
 
 def xgrid_view(ws, layout, m, N):
-    """complex64 view X[z][y][kx] (z < the slab height) of grid m inside the workspace
-    returned by stage_xgrids."""
+    """complex64 values X[z][y][kx] (z < the slab height) of grid m inside the workspace
+    returned by stage_xgrids, as (planes, N, kx, 2) float32: a view, or at N = 2048, where
+    the library stores X tile-major ([z][kx / 4][y][kx % 4]), a reordered copy."""
     import torch
     off, kx, planes = layout[m]
     nbytes = planes * N * kx * 8
-    raw = ws[off:off + nbytes]
-    return raw.view(torch.float32).view(planes, N, kx, 2)
+    raw = ws[off:off + nbytes].view(torch.float32)
+    if N >= 2048:
+        return raw.view(planes, kx // 4, N, 4, 2).permute(0, 2, 1, 3, 4).reshape(planes, N, kx, 2)
+    return raw.view(planes, N, kx, 2)
 
 
 def autotune(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, reps: int = 3, workspace: Workspace | None = None):

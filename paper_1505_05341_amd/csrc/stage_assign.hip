@@ -342,7 +342,11 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   const int Kx = a.Kx;
   if (tid < Kx) {
     const int kx = tid;
-    const size_t o = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx + kx;
+    size_t o;
+    if constexpr (N >= 2048)  // tile-major: [plane][kx / 4][y][kx % 4]
+      o = (size_t)(a.pbase + zs) * N * (size_t)Kx + (size_t)(kx >> 2) * (4 * N) + 4 * y + (kx & 3);
+    else
+      o = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx + kx;
     const int ik = XSwizzle()(kx), im = XSwizzle()((N - kx) & (N - 1));
     // the grid stride is opaque here: otherwise the compiler forms all GK + ND products
     // with it up front and holds them in (spilled) scalar registers through the kernel

@@ -80,10 +80,18 @@ __device__ __forceinline__ void load_member(const float2* __restrict__ X, const 
   using F = Fft<N, EC>;
   const int tid = col_hide<EC>(tid0);
   const int c = tid % TK, t = tid / TK;
-  const float2* __restrict__ src =
-      X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + kt * TK + c;
+  if constexpr (N >= 2048) {  // tile-major X: [plane][kx / TK][y][kx % TK]
+    static_assert(TK == 4, "tile-major X is written with 4-column tiles");
+    const float2* __restrict__ src =
+        X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + (size_t)kt * TK * N + c;
 #pragma unroll
-  for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * a.Kx];
+    for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * TK];
+  } else {
+    const float2* __restrict__ src =
+        X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + kt * TK + c;
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * a.Kx];
+  }
 }
 
 template <int N, int TK, int EC>
