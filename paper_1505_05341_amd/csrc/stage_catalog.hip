@@ -266,8 +266,11 @@ __device__ __forceinline__ uint32_t block_scan_lds(uint32_t* a, int n) {
 // threads store consecutive slots of one bucket (runs of ~tile/buckets particles)
 // instead of scattering 16-byte stores over all buckets, which costs a partial-line
 // write per particle.
+// Tiles of 6144 particles (6 per thread): the largest multiple of the block that leaves
+// the staging within the 160 KB of LDS at N = 2048 (24 KB of bucket tables + 120 KB);
+// measured 7-8% faster than 4096 at 512^3 and 1024^3 (longer runs, fewer tile rounds).
 constexpr int kSortThreads = 1024;
-constexpr int kSortTile = 4096;
+constexpr int kSortTile = 6144;
 constexpr int kSortPer = kSortTile / kSortThreads;
 
 // LDS of one staged scatter: cur, tcnt, gb (uint32[nb] each), stage float4[tile],
