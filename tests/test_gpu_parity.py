@@ -413,9 +413,11 @@ def test_particles_on_cell_edges_and_box_faces(pk):
         compare(got, ref, cfg)
 
 
-def test_all_galaxies_in_one_cell(pk):
+@pytest.mark.parametrize("assign", [2, 3])
+def test_all_galaxies_in_one_cell(pk, assign):
     """Extreme clustering: every galaxy in one cell, so one grid row holds them all (many
-    LDS chunks, one overloaded cell in the in-row sort), randoms uniform."""
+    LDS chunks, one overloaded cell in the in-row sort and in the x pass's walk over the
+    S base cells of a target cell), randoms uniform; CIC and TSC."""
     N, L = 64, 600.0
     box_min = (-300.0, -300.0, 700.0)
     rng = np.random.default_rng(31)
@@ -423,7 +425,7 @@ def test_all_galaxies_in_one_cell(pk):
     corner = np.asarray(box_min) + np.array([17, 40, 5]) * H
     gal = _grid_catalog(corner[None, :] + rng.random((6000, 3)) * H, 1.0, 1e-4)
     ran = catalogs.uniform_box(20000, box_min, L, 32, 1e-4)
-    cfg = catalogs.config_dict(N, box_min, L, assign=3)
+    cfg = catalogs.config_dict(N, box_min, L, assign=assign)
     got, ref = run_both(pk, gal, ran, cfg)
     compare(got, ref, cfg)
 
