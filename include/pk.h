@@ -188,6 +188,39 @@ pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
                           size_t* offset, int32_t* kx_count);
 
+/* Stage entry point for tests: runs everything pk_multipoles runs up to and including
+ * the transforms along y of every slab (same kernels), then stops, leaving in the
+ * workspace the z-power groups H of the contraction of Sec. 3, Eqs. (10) and (12):
+ * A_n = |t|^-n sum_{a+b+c=n} (n!/(a! b! c!)) tx^a ty^b tz^c G_abc with t = 2 n_vec / N
+ * (k-hat = t / |t|) and G_abc the transform of F rhat_x^a rhat_y^b rhat_z^c, is regrouped by
+ * the power c of tz before the transform along z:
+ *   H_(n,c)(kx, ky, z) = sum_{a+b=n-c} (n!/(a! b! c!)) tx^a ty^b Y_abc(kx, ky, z),
+ * Y_abc = the unnormalised transform along x and y (e^{-2 pi i (kx x + ky y)/N}) of plane z
+ * of F rhat^(a,b,c), for kx in [0, Kx) and |ky| <= ky_max(kx tile) (the modes of the
+ * binned sphere). Queued on `hip_stream`. Errors as pk_multipoles_async. */
+pk_status pk_stage_fft(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
+                       void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Where pk_stage_fft leaves group `group` (0 .. 1/4/9/16 - 1, in the order of pk_zgroup)
+ * for kx tile `kx_tile` (columns kx = kx_tile * tile_cols .. + tile_cols - 1, up to
+ * Kx = nbins dn rounded up to tile_cols): complex64 values at byte `offset` of the
+ * workspace, laid out [z][ky + ky_max][column] for z < N, |ky| <= ky_max. */
+pk_status pk_hgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t group, int32_t kx_tile,
+                          size_t* offset, int32_t* ky_max, int32_t* tile_cols);
+
+/* Degree n and power c of tz of z-power group `group`: the groups run over n = 0, 2, ..
+ * ell_max and, for each n, c = 0 .. n. PK_EINVAL past the last group. */
+pk_status pk_zgroup(int32_t ell_max, int32_t group, int32_t* degree, int32_t* z_power);
+
+/* Stage entry point for tests: the transform along z, the k-hat contraction of Eqs. (10)
+ * and (12), the compensation, the shell binning and the finalisation of Eqs. (6)-(8) and
+ * (3), on the groups H and the catalogue scalars that pk_stage_fft left in `workspace`
+ * for the same configuration and catalogue sizes (the same kernels as pk_multipoles).
+ * Synchronous; fills `out` like pk_multipoles (input errors flagged by the earlier stage
+ * are returned here). */
+pk_status pk_stage_contract(const pk_config* cfg, int64_t n_gal, int64_t n_ran, void* workspace,
+                            size_t workspace_bytes, pk_result* out, void* hip_stream);
+
 /* The slab height the plan of this configuration uses (cfg->x_planes, or the automatic
  * choice when that is 0). PK_EINVAL / PK_ENOTSUP for an invalid configuration. */
 pk_status pk_x_planes(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t* planes);
@@ -261,6 +294,13 @@ pk_status pk_mlp_gradients(const pk_mlp_shape* shape, const void* state, const f
 /* One Adam step (b1 0.9, b2 0.999, eps 1e-8; `step` counts from 1) on the batch. */
 pk_status pk_mlp_train_step(const pk_mlp_shape* shape, void* state, const float* d_x, const float* d_t, int64_t rows,
                             float lr, int32_t step, float* d_loss, void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+/* The same Adam step (the kernel pk_mlp_train_step ends with) applied with a caller's
+ * gradient vector d_grads (device float32, pk_mlp_num_params values, canonical order):
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * w -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), in FP32 elementwise
+ * (Kingma & Ba's Adam), then the BF16 copies of the weights are refreshed. */
+pk_status pk_mlp_adam_apply(const pk_mlp_shape* shape, void* state, const float* d_grads, float lr, int32_t step,
                             void* hip_stream);
 
 /* Number of LOS-weighted grids for ell_max (1, 7, 22, 50), and the exponents of grid m. */

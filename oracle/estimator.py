@@ -40,6 +40,7 @@ notes of the repository):
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -405,3 +406,173 @@ def x_transformed_row(pos, wprime, cfg: Config, m, iy, iz):
                 row += np.bincount(cx, weights=vals[sel] * wx[aa][sel] * wy[bb][sel] * wz[cc][sel],
                                    minlength=N)
     return np.fft.fft(row)
+
+
+# ----------------------------------------------------------------------------
+# Lean forms for the largest grids (N = 512, 1024 on a host)
+# ----------------------------------------------------------------------------
+
+def deposit(pos, values, cfg: Config):
+    """The same periodic CIC/TSC deposit as assign_to_grid, with the cells and weights of
+    every stencil offset gathered first and summed by one bincount over the grid (for
+    catalogues far smaller than the grid, where a dense bincount of N^3 bins per stencil
+    offset would dominate the cost)."""
+    N = cfg.N
+    u = grid_units(pos, cfg.box_min, cfg.L, N)
+    values = np.asarray(values, dtype=np.float64)
+    ix, ox, wx = axis_weights(u[:, 0], cfg.assign)
+    iy, oy, wy = axis_weights(u[:, 1], cfg.assign)
+    iz, oz, wz = axis_weights(u[:, 2], cfg.assign)
+    cells, weights = [], []
+    for a, dx in enumerate(ox):
+        cx = (ix + dx) % N
+        for b, dy in enumerate(oy):
+            cy = (iy + dy) % N
+            wxy = wx[a] * wy[b]
+            for c, dz in enumerate(oz):
+                cz = (iz + dz) % N
+                cells.append((cx * N + cy) * N + cz)
+                weights.append(values * wxy * wz[c])
+    g = np.bincount(np.concatenate(cells), weights=np.concatenate(weights), minlength=N * N * N)
+    return g.reshape(N, N, N)
+
+
+class _HalfLattice:
+    """The binned modes of the half lattice nz in [0, N/2), chunk by chunk of kx planes,
+    with every per-mode factor the shell sums need: the flat index of the mode inside its
+    chunk, its bin, |n|, k-hat, the multiplicity (1 on nz = 0, 2 elsewhere: the modes
+    with nz < 0 are the complex conjugates of those with nz > 0), 1/W^2 and the noise
+    factor C/W^2 (or 1). Computed once and reused for every grid."""
+
+    def __init__(self, cfg: Config, planes):
+        N = cfg.N
+        nv = mode_lattice(N)
+        nzv = np.arange(N // 2, dtype=np.int64)
+        Wi, Ci = window_and_alias(N, cfg.assign)
+        self.chunks = []
+        for x0 in range(0, N, planes):
+            x1 = min(N, x0 + planes)
+            nx = nv[x0:x1][:, None, None]
+            ny = nv[None, :, None]
+            nz = nzv[None, None, :]
+            n2 = (nx * nx + ny * ny + nz * nz).reshape(-1)
+            b = isqrt_array(n2) // cfg.dn
+            idx = np.nonzero((n2 > 0) & (b < cfg.nbins))[0]
+            if idx.size == 0:
+                continue
+            shape = (x1 - x0, N, N // 2)
+            jx, jy, jz = np.unravel_index(idx, shape)
+            mx, my, mz = nv[x0:x1][jx], nv[jy], nzv[jz]
+            kn = np.sqrt(n2[idx].astype(np.float64))
+            mult = np.where(mz == 0, 1.0, 2.0)
+            if cfg.compensate == 0:
+                inv_w2 = np.ones(idx.size)
+                cnoise = np.ones(idx.size)
+            else:
+                W = Wi[x0:x1][jx] * Wi[jy] * Wi[jz]
+                inv_w2 = 1.0 / (W * W)
+                cnoise = np.ones(idx.size) if cfg.compensate == 1 else Ci[x0:x1][jx] * Ci[jy] * Ci[jz] * inv_w2
+            self.chunks.append(dict(x0=x0, x1=x1, idx=idx, bin=b[idx], k=kn, mult=mult, inv_w2=inv_w2,
+                                    cnoise=cnoise, kh=(mx / kn, my / kn, mz / kn)))
+
+    @staticmethod
+    def take(grid_k, ch):
+        """The values of a half-lattice array at the chunk's binned modes."""
+        return grid_k[ch["x0"]:ch["x1"]].reshape(-1)[ch["idx"]]
+
+
+def _half_spectrum(grid, workers):
+    """The transform of a real grid on the half lattice nz in [0, N/2): the library's
+    real-input FFT (the same unnormalised e^{-2 pi i n.j/N} transform as fft3)."""
+    import scipy.fft as sfft
+    N = grid.shape[0]
+    return sfft.rfftn(grid, workers=workers)[:, :, :N // 2]
+
+
+def pk_multipoles_lean(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=None, ran_nbar=None,
+                       workers=None, planes=16, log=None):
+    """Same result as pk_multipoles, in the memory of about two transformed grids.
+
+    Two facts of the same definition make it lean; the steps are otherwise those of
+    pk_multipoles (Secs. 2-4) in the same order:
+
+      * the monomial grids are real, so G_m(-n) = conj G_m(n), and every k-hat monomial
+        of even degree is even in k-hat: Re[A_0 A_n^*], W^2, the noise and the bin of -n
+        equal those of n. The full-lattice shell sums are the sums over the half lattice
+        nz >= 0 with weight 1 on the nz = 0 plane and 2 elsewhere (the plane nz = -N/2 is
+        never binned when nbins dn <= N/2);
+      * Re[A_0 A_n^*] = sum_{|m| = n} c_m khat^m Re[A_0 G_m^*] (Eqs. 10, 12; khat^m is real)
+        is linear in the grids, so the shell sums of Q_n are accumulated grid by grid
+        and only A_0 (at the binned modes) and the current G_m are held.
+    """
+    assert cfg.nbins * cfg.dn <= cfg.N // 2, "bins must stay below the Nyquist frequency"
+    workers = workers or (os.cpu_count() or 1)
+    alpha, I, S = catalogue_scalars(gal_w, ran_w, gal_nbar, ran_nbar, cfg.norm_from)
+    pos = np.concatenate([np.asarray(gal_pos, np.float64), np.asarray(ran_pos, np.float64)])
+    wprime = signed_weights(gal_w, ran_w, alpha)
+    rh = unit_los(pos, cfg.observer, cfg.los)
+    nb = cfg.nbins
+    lat = _HalfLattice(cfg, planes)
+    sums = {"count": np.zeros(nb, np.int64), "k": np.zeros(nb), "noise": np.zeros(nb)}
+    for n in range(0, cfg.ell_max + 1, 2):
+        sums[f"Q{n}"] = np.zeros(nb)
+    a0 = []
+    for (a, b, c), coef in los_monomials(cfg.ell_max):
+        n = a + b + c
+        vals = wprime * rh[:, 0] ** a * rh[:, 1] ** b * rh[:, 2] ** c
+        Gm = _half_spectrum(deposit(pos, vals, cfg), workers)
+        for j, ch in enumerate(lat.chunks):
+            bv, mult = ch["bin"], ch["mult"]
+            g = lat.take(Gm, ch)
+            if n == 0:
+                a0.append(g)
+                q = mult * np.real(g * np.conj(g)) * ch["inv_w2"]
+                sums["Q0"] += np.bincount(bv, weights=q, minlength=nb)[:nb]
+                sums["count"] += np.bincount(bv, weights=mult, minlength=nb)[:nb].astype(np.int64)
+                sums["k"] += np.bincount(bv, weights=mult * ch["k"], minlength=nb)[:nb]
+                sums["noise"] += np.bincount(bv, weights=mult * S * ch["cnoise"], minlength=nb)[:nb]
+                continue
+            khx, khy, khz = ch["kh"]
+            q = mult * coef * khx ** a * khy ** b * khz ** c * np.real(a0[j] * np.conj(g)) * ch["inv_w2"]
+            sums[f"Q{n}"] += np.bincount(bv, weights=q, minlength=nb)[:nb]
+        del Gm
+        if log:
+            log("grid %s done" % ((a, b, c),))
+    k_eff, P, noise = legendre_combination(sums, cfg, I)
+    return Result(k_eff=k_eff, nmodes=sums["count"], P=P, noise=noise, alpha=alpha, I=I, S=S, sums=sums)
+
+
+def plane_parallel_multipoles(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=None, ran_nbar=None,
+                              workers=None, planes=16):
+    """The estimator with the line of sight fixed to +z, in the plane-parallel form that
+    needs one transform: P_l = (2l + 1) <|A_0|^2 L_l(k_z / k) / W^2> / I, minus the noise
+    for l = 0 (Sec. 2, Eqs. 2-4 with r-hat = z for every particle, shell-averaged as in
+    Eqs. 6-8). It is the cross-path the 22-grid decomposition of Sec. 3 must reduce to
+    when every F r-hat^m grid is r_z^n times F. Shell sums over the half lattice as in
+    pk_multipoles_lean."""
+    from . import direct
+    assert cfg.nbins * cfg.dn <= cfg.N // 2, "bins must stay below the Nyquist frequency"
+    workers = workers or (os.cpu_count() or 1)
+    alpha, I, S = catalogue_scalars(gal_w, ran_w, gal_nbar, ran_nbar, cfg.norm_from)
+    pos = np.concatenate([np.asarray(gal_pos, np.float64), np.asarray(ran_pos, np.float64)])
+    wprime = signed_weights(gal_w, ran_w, alpha)
+    A0 = _half_spectrum(deposit(pos, wprime, cfg), workers)
+    nb = cfg.nbins
+    ells = tuple(range(0, cfg.ell_max + 1, 2))
+    cnt, ks, ns = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    qs = {ell: np.zeros(nb) for ell in ells}
+    for ch in _HalfLattice(cfg, planes).chunks:
+        bv, mult = ch["bin"], ch["mult"]
+        mu = ch["kh"][2]
+        p = mult * np.abs(_HalfLattice.take(A0, ch)) ** 2 * ch["inv_w2"]
+        cnt += np.bincount(bv, weights=mult, minlength=nb)[:nb]
+        ks += np.bincount(bv, weights=mult * ch["k"], minlength=nb)[:nb]
+        ns += np.bincount(bv, weights=mult * S * ch["cnoise"], minlength=nb)[:nb]
+        for ell in ells:
+            qs[ell] += np.bincount(bv, weights=(2 * ell + 1) * p * direct.legendre(ell, mu), minlength=nb)[:nb]
+    ok = cnt > 0
+    den = I * np.where(ok, cnt, 1.0)
+    noise = np.where(ok, ns / den, 0.0)
+    P = {ell: np.where(ok, qs[ell] / den - (noise if ell == 0 else 0.0), 0.0) for ell in ells}
+    k_eff = np.where(ok, (2.0 * np.pi / cfg.L) * ks / np.where(ok, cnt, 1.0), 0.0)
+    return Result(k_eff=k_eff, nmodes=cnt.astype(np.int64), P=P, noise=noise, alpha=alpha, I=I, S=S)

@@ -13,7 +13,10 @@ written out from the definitions:
   Adam      (Kingma & Ba 2015) m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
             theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
 
-Weights are stored [in, out] (row-major), as the device kernels store them.
+Weights are stored [in, out] (row-major), as the device kernels store them. forward and
+backward take an optional rounding of the operands of every product, so that a device
+computing in a narrower format (bfloat16 operands, wider accumulation) can be compared
+element by element with the same network evaluated in FP64 from the same rounded operands.
 """
 from __future__ import annotations
 
@@ -40,12 +43,31 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, x):
+def bf16_round(a):
+    """Round to the nearest bfloat16 value (8 significant bits: the sign, the 8 exponent bits
+    and the top 7 fraction bits of an IEEE single), ties to even, returned as float64.
+    The value is first rounded to float32 (as the device holds it)."""
+    f = np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    keep = (u >> 16) & 1                       # lowest kept bit: ties go to the even neighbour
+    r = ((u + 0x7FFF + keep) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(a):
+    return a
+
+
+def forward(params, x, operand_round=None):
+    """operand_round (optional) is applied to both operands of every product (the input
+    or hidden activations and the weights), as a device that multiplies in a narrower
+    format does; biases, pre-activations and the output stay in FP64."""
+    rnd = operand_round or _identity
     h = np.asarray(x, np.float64)
     cache = [h]
     zs = []
     for i, (W, b) in enumerate(params):
-        z = h @ W + b
+        z = rnd(h) @ rnd(W) + b
         if i < len(params) - 1:
             zs.append(z)
             h = silu(z)
@@ -60,15 +82,18 @@ def mse(y, t):
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
-def backward(params, state, dy):
+def backward(params, state, dy, operand_round=None):
+    """operand_round (optional) is applied to both operands of every product, as in
+    forward; the bias gradients are column sums of the unrounded dz."""
+    rnd = operand_round or _identity
     cache, zs = state
     grads = [None] * len(params)
     dz = dy
     for i in range(len(params) - 1, -1, -1):
         W, _ = params[i]
-        grads[i] = (cache[i].T @ dz, dz.sum(axis=0))
+        grads[i] = (rnd(cache[i]).T @ rnd(dz), dz.sum(axis=0))
         if i > 0:
-            dz = (dz @ W.T) * silu_grad(zs[i - 1])
+            dz = (rnd(dz) @ rnd(W).T) * silu_grad(zs[i - 1])
     return grads
 
 

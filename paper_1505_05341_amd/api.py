@@ -158,6 +158,47 @@ def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: W
     return ws, layout
 
 
+def stage_fft(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
+    """Runs up to the transforms along y of every slab and returns the workspace tensor,
+    which then holds the z-power groups H (see hgrid_view)."""
+    import torch
+    lib = native.load()
+    c = native.make_config(cfg)
+    nbytes = native.workspace_size(cfg, gal.n, ran.n)
+    ws = (workspace or Workspace()).get(nbytes)
+    native.check(lib.pk_stage_fft(ctypes.byref(c), ctypes.byref(gal.c_struct()), ctypes.byref(ran.c_struct()),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), native.current_stream()))
+    torch.cuda.synchronize()
+    return ws
+
+
+def hgrid_view(ws, cfg: dict, n_gal: int, n_ran: int, group: int, kx_tile: int):
+    """complex64 H[z][ky + M][column] of one z-power group and kx tile in the workspace left by
+    stage_fft, as (N, 2 M + 1, tile columns, 2) float32, and M."""
+    import torch
+    lib = native.load()
+    c = native.make_config(cfg)
+    off, M, tk = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int32()
+    native.check(lib.pk_hgrid_layout(ctypes.byref(c), n_gal, n_ran, group, kx_tile, ctypes.byref(off),
+                                     ctypes.byref(M), ctypes.byref(tk)))
+    N, M, tk, off = c.N, int(M.value), int(tk.value), int(off.value)
+    nbytes = N * (2 * M + 1) * tk * 8
+    return ws[off:off + nbytes].view(torch.float32).view(N, 2 * M + 1, tk, 2), M
+
+
+def stage_contract(ws, cfg: dict, n_gal: int, n_ran: int):
+    """The z transform, contraction, binning and finalisation on the workspace left by
+    stage_fft; returns the same dictionary as pk_multipoles."""
+    lib = native.load()
+    c = native.make_config(cfg)
+    host = _HostResult(c)
+    res = native.PkResult()
+    host.fill(res)
+    native.check(lib.pk_stage_contract(ctypes.byref(c), n_gal, n_ran, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       ctypes.byref(res), native.current_stream()))
+    return host.as_dict(res)
+
+
 def xgrid_view(ws, layout, m, N):
     """complex64 values X[z][y][kx] (z < the slab height) of grid m inside the workspace
     returned by stage_xgrids, as (planes, N, kx, 2) float32: a view, or at N = 2048, where

@@ -350,3 +350,39 @@ def _inside_device(pos64, box_min, L):
 
 def device_catalog_to_host(cat):
     return Catalog(cat.pos.cpu().numpy(), cat.w.cpu().numpy(), cat.nbar.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------------
+# Host-made catalogues for parity at the benchmark grids. Small enough for the FP64
+# oracle, with the geometry and recipe of the benchmark workloads; the oracle's results
+# for them are stored under tests/golden/ by a script that calls only the oracle.
+# ---------------------------------------------------------------------------------
+
+def desi_geometry_small(seed=31, nbar=3.0e-6, ran_factor=5.0, N=1024, **cfg_kw):
+    """The DESI-scale geometry (L = 4000 Mpc/h centred at (0, 0, 3000), observer at the
+    origin, lognormal RSD field with the same power law, f = 0.75, b = 2, FKP P0 = 1e4)
+    at a low density: about 1.9e5 galaxies + 9.6e5 randoms, on the 1024^3 TSC plan of the
+    benchmark (22 grids, bins of width 2 k_f up to the Nyquist frequency)."""
+    gal, ran, box_min = lognormal_rsd(N_field=256, L=4000.0, center=(0.0, 0.0, 3000.0), nbar=nbar, seed=seed,
+                                      ran_factor=ran_factor)
+    kw = dict(assign=3, ell_max=4, dn=2)
+    kw.update(cfg_kw)
+    return gal, ran, config_dict(N, box_min, 4000.0, **kw)
+
+
+def clustered_geometry_small(seed=32, nbar=2.0e-5, ran_factor=5.0, N=512, **cfg_kw):
+    """The clustered 512^3 geometry (L = 2500 Mpc/h centred at (0, 0, 2000), same recipe)
+    at a low density: about 3.1e5 galaxies + 1.6e6 randoms, on the 512^3 CIC plan of the
+    benchmark (bins of width 2 k_f), observed from an observer off the origin."""
+    gal, ran, box_min = lognormal_rsd(N_field=256, L=2500.0, center=(0.0, 0.0, 2000.0), nbar=nbar, seed=seed,
+                                      ran_factor=ran_factor)
+    kw = dict(assign=2, ell_max=4, dn=2, observer=(120.0, -75.0, 40.0))
+    kw.update(cfg_kw)
+    return gal, ran, config_dict(N, box_min, 2500.0, **kw)
+
+
+def checksum(gal, ran):
+    """Counts and FP64 sums of the positions and weights: identifies a generated catalogue."""
+    return {"n_gal": gal.n, "n_ran": ran.n,
+            "pos_sum": [float(np.sum(c.pos[:, ax], dtype=np.float64)) for c in (gal, ran) for ax in range(3)],
+            "w_sum": [float(np.sum(gal.w, dtype=np.float64)), float(np.sum(ran.w, dtype=np.float64))]}

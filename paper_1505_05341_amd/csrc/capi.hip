@@ -206,14 +206,18 @@ static pk_status hip_fail(hipError_t e, const char* where) {
   return fail(PK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-static pk_status prepare(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* ws,
-                         size_t ws_bytes, Plan* p) {
+static pk_status prepare_plan(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, Plan* p) {
   pk_status st = check_catalog(gal, cfg && cfg->norm_from == 1, "galaxy");
   if (st != PK_OK) return st;
   st = check_catalog(ran, cfg && cfg->norm_from == 0, "random");
   if (st != PK_OK) return st;
   const char* why;
-  st = make_plan(cfg, gal->n, ran->n, p, &why);
+  return make_plan(cfg, gal->n, ran->n, p, &why);
+}
+
+static pk_status prepare(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* ws,
+                         size_t ws_bytes, Plan* p) {
+  const pk_status st = prepare_plan(cfg, gal, ran, p);
   if (st != PK_OK) return st;
   if (!ws || ws_bytes < p->total)
     return fail(PK_EWORKSPACE, "workspace needs " + std::to_string(p->total) + " bytes, got " + std::to_string(ws_bytes));
@@ -273,13 +277,13 @@ static hipError_t pipe_for_device(Pipe** out) {
 // passes run in order on `s`; otherwise the y passes run on the second stream, each after
 // its slab's x pass (an event on `s`), and an x pass that reuses a slot waits for the y
 // pass that read it; `s` finally waits for the last y pass.
-static hipError_t run_slabs(const Plan& p, char* ws, hipStream_t s, bool stop_after_x, bool timed) {
+static hipError_t run_slabs(const Plan& p, char* ws, hipStream_t s, bool stop_after_x, bool timed, bool one_stream) {
   const int nslab = p.N / p.xs;
   hipError_t e;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
   Pipe* pp = nullptr;
-  if (nslab > 1 && !stop_after_x && cs == hipStreamCaptureStatusNone && p.xr <= kPipeEvents) {
+  if (nslab > 1 && !stop_after_x && !one_stream && cs == hipStreamCaptureStatusNone && p.xr <= kPipeEvents) {
     if ((e = pipe_for_device(&pp)) != hipSuccess) return e;
   }
   if (!pp) {
@@ -306,10 +310,15 @@ static hipError_t run_slabs(const Plan& p, char* ws, hipStream_t s, bool stop_af
   return hipStreamWaitEvent(s, pp->ey[(nslab - 1) % kPipeEvents], 0);
 }
 
+// Where a call stops: after the x transforms of the first slab (X left in the workspace),
+// after the y transforms of every slab (H left in the workspace), or at the end.
+enum class Stop { kAfterX, kAfterY, kNone };
+
 static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catalog& ran, char* ws, double* d_result,
-                            hipStream_t s, bool stop_after_x) {
+                            hipStream_t s, Stop stop, bool one_stream = false) {
   hipError_t e;
-  const bool timed = g_timing.enabled && !stop_after_x;
+  const bool stop_after_x = stop == Stop::kAfterX;
+  const bool timed = g_timing.enabled && stop == Stop::kNone && !one_stream;
   if (timed) {
     int dev = -1;
     hipGetDevice(&dev);
@@ -329,8 +338,9 @@ static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catal
   if (timed) mark(3, s);
   // with one slab (xs = N) the x and y stages are timed apart; with several, "assign_x"
   // covers both
-  if ((e = run_slabs(p, ws, s, stop_after_x, timed)) != hipSuccess) return hip_fail(e, "x and y transforms");
-  if (stop_after_x) return PK_OK;
+  if ((e = run_slabs(p, ws, s, stop_after_x, timed, one_stream)) != hipSuccess)
+    return hip_fail(e, "x and y transforms");
+  if (stop != Stop::kNone) return PK_OK;
   if (timed && p.xs != p.N) mark(4, s);
   if (timed) mark(5, s);
   if ((e = launch_zpass(p, ws, s)) != hipSuccess) return hip_fail(e, "z transform and binning");
@@ -342,6 +352,9 @@ static pk_status run_stages(const Plan& p, const pk_catalog& gal, const pk_catal
   }
   return PK_OK;
 }
+
+// Copies the device result of a call to the caller's host arrays (waits for the stream).
+static pk_status fetch_result(const Plan& p, const double* d_res, hipStream_t s, pk_result* out);
 
 static pk_status flags_status(int flags);
 
@@ -359,6 +372,15 @@ static pk_status unpack_result(const double* r, int nb, int nl, pk_result* o) {
   o->I = tail[1];
   o->S = tail[2];
   return PK_OK;
+}
+
+static pk_status fetch_result(const Plan& p, const double* d_res, hipStream_t s, pk_result* out) {
+  std::vector<double> h((size_t)p.result_doubles);
+  hipError_t e = hipMemcpyAsync(h.data(), d_res, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "result copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  return unpack_result(h.data(), p.nbins, p.ell_max / 2 + 1, out);
 }
 
 static pk_status flags_status(int flags) {
@@ -397,7 +419,7 @@ pk_status pk_multipoles_async(const pk_config* cfg, const pk_catalog* gal, const
   pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
   if (st != PK_OK) return st;
   if (!d_result) return fail(PK_EINVAL, "null result pointer");
-  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), d_result, (hipStream_t)hip_stream, false);
+  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), d_result, (hipStream_t)hip_stream, Stop::kNone);
 }
 
 pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
@@ -409,14 +431,9 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = (hipStream_t)hip_stream;
   double* d_res = at<double>(ws, p.off_result);
-  st = run_stages(p, *gal, *ran, ws, d_res, s, false);
+  st = run_stages(p, *gal, *ran, ws, d_res, s, Stop::kNone);
   if (st != PK_OK) return st;
-  std::vector<double> h((size_t)p.result_doubles);
-  hipError_t e = hipMemcpyAsync(h.data(), d_res, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return hip_fail(e, "result copy");
-  e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-  return unpack_result(h.data(), p.nbins, p.ell_max / 2 + 1, out);
+  return fetch_result(p, d_res, s, out);
 }
 
 // ------------------------------------------------------------------- FFT schedules
@@ -608,7 +625,7 @@ pk_status pk_multipoles_batch(const pk_config* cfgs, const pk_catalog* gals, con
       g_timing.enabled = timing;
       return batch_fail_cleanup(hip_fail(e, "begin capture"), ls, lanes, gs, ev, 3);
     }
-    st = run_stages(p, gals[i], rans[i], lws, d_res + (size_t)i * rd, ls[l], false);
+    st = run_stages(p, gals[i], rans[i], lws, d_res + (size_t)i * rd, ls[l], Stop::kNone);
     e = hipStreamEndCapture(ls[l], &graph);
     if (st != PK_OK || e != hipSuccess) {
       if (graph) hipGraphDestroy(graph);
@@ -664,7 +681,63 @@ pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_
   Plan p;
   pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
   if (st != PK_OK) return st;
-  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), nullptr, (hipStream_t)hip_stream, true);
+  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), nullptr, (hipStream_t)hip_stream, Stop::kAfterX);
+}
+
+pk_status pk_stage_fft(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, void* workspace,
+                       size_t workspace_bytes, void* hip_stream) {
+  Plan p;
+  pk_status st = prepare(cfg, gal, ran, workspace, workspace_bytes, &p);
+  if (st != PK_OK) return st;
+  return run_stages(p, *gal, *ran, static_cast<char*>(workspace), nullptr, (hipStream_t)hip_stream, Stop::kAfterY);
+}
+
+pk_status pk_stage_contract(const pk_config* cfg, int64_t n_gal, int64_t n_ran, void* workspace,
+                            size_t workspace_bytes, pk_result* out, void* hip_stream) {
+  Plan p;
+  const char* why;
+  pk_status st = make_plan(cfg, n_gal, n_ran, &p, &why);
+  if (st != PK_OK) return st;
+  if (!out) return fail(PK_EINVAL, "null result");
+  if (!workspace || workspace_bytes < p.total)
+    return fail(PK_EWORKSPACE, "workspace needs " + std::to_string(p.total) + " bytes, got " +
+                                   std::to_string(workspace_bytes));
+  if (((uintptr_t)workspace & 255) != 0) return fail(PK_EWORKSPACE, "workspace must be 256-byte aligned");
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* d_res = at<double>(ws, p.off_result);
+  hipError_t e;
+  if ((e = launch_zpass(p, ws, s)) != hipSuccess) return hip_fail(e, "z transform and binning");
+  if ((e = launch_finalize(p, ws, d_res, s)) != hipSuccess) return hip_fail(e, "finalize");
+  return fetch_result(p, d_res, s, out);
+}
+
+pk_status pk_hgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t group, int32_t kx_tile,
+                          size_t* offset, int32_t* ky_max, int32_t* tile_cols) {
+  Plan p;
+  const char* why;
+  pk_status st = make_plan(cfg, n_gal, n_ran, &p, &why);
+  if (st != PK_OK) return st;
+  if (group < 0 || group >= p.groups.ngroups) return fail(PK_EINVAL, "group index out of range");
+  if (kx_tile < 0 || kx_tile >= p.nkt) return fail(PK_EINVAL, "kx tile out of range");
+  if (!offset || !ky_max || !tile_cols) return fail(PK_EINVAL, "null output pointer");
+  *offset = p.off_H + sizeof(float) * 2 * ((size_t)group * p.H_group_stride + (size_t)p.tiles.regoff[kx_tile]);
+  *ky_max = p.tiles.M[kx_tile];
+  *tile_cols = p.TK;
+  return PK_OK;
+}
+
+pk_status pk_zgroup(int32_t ell_max, int32_t group, int32_t* degree, int32_t* z_power) {
+  if (!ell_ok(ell_max) || !degree || !z_power) return fail(PK_EINVAL, "bad ell_max or null pointer");
+  int g = 0;
+  for (int n = 0; n <= ell_max; n += 2)
+    for (int c = 0; c <= n; ++c, ++g)
+      if (g == group) {
+        *degree = n;
+        *z_power = c;
+        return PK_OK;
+      }
+  return fail(PK_EINVAL, "group index out of range");
 }
 
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m, size_t* offset,

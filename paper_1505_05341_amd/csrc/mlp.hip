@@ -437,6 +437,18 @@ static void backward(const MlpPlan& P, void* state, const float* t, float* loss,
   }
 }
 
+// One Adam step (b1 0.9, b2 0.999, eps 1e-8, bias corrections 1 - b^step) of the FP32
+// master weights with the gradient vector g (canonical order), then fresh BF16 copies.
+static hipError_t adam(const MlpPlan& P, void* state, const float* g, float lr, int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  const int64_t n = P.d.nparams;
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ptr<float>(state, P.st_w),
+                     ptr<float>(state, P.st_m), ptr<float>(state, P.st_v), g, n, lr, b1, b2, 1e-8f, c1, c2);
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : refresh_copies(P, state, s);
+}
+
 }  // namespace pk
 
 using namespace pk;
@@ -519,13 +531,15 @@ pk_status pk_mlp_train_step(const pk_mlp_shape* shape, void* state, const float*
   hipStream_t s = (hipStream_t)hip_stream;
   forward(P, state, d_x, workspace, s);
   backward(P, state, d_t, d_loss, workspace, s);
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-  const int64_t n = P.d.nparams;
-  hipLaunchKernelGGL(mlp_adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ptr<float>(state, P.st_w),
-                     ptr<float>(state, P.st_m), ptr<float>(state, P.st_v), ptr<const float>(workspace, P.ws_grad), n, lr,
-                     b1, b2, 1e-8f, c1, c2);
-  if (refresh_copies(P, state, s) != hipSuccess) return PK_EDEVICE;
+  if (adam(P, state, ptr<const float>(workspace, P.ws_grad), lr, step, s) != hipSuccess) return PK_EDEVICE;
+  return hipGetLastError() == hipSuccess ? PK_OK : PK_EDEVICE;
+}
+
+pk_status pk_mlp_adam_apply(const pk_mlp_shape* shape, void* state, const float* d_grads, float lr, int32_t step,
+                            void* hip_stream) {
+  MlpPlan P;
+  if (!mlp_plan(shape, 0, &P) || !state || !d_grads || step < 1) return PK_EINVAL;
+  if (adam(P, state, d_grads, lr, step, (hipStream_t)hip_stream) != hipSuccess) return PK_EDEVICE;
   return hipGetLastError() == hipSuccess ? PK_OK : PK_EDEVICE;
 }
 

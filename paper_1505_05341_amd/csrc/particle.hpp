@@ -18,6 +18,16 @@ __device__ __forceinline__ float grid_coord(float x, float bmin, float invH) {
   return __fmul_rn(__fsub_rn(x, bmin), invH);
 }
 
+// Squared distance of a particle to the observer in FP32, with the rounding of every
+// operation fixed (no contraction left to the compiler), so that the validity test of
+// the sort and the line of sight of the assignment take the same value: a particle
+// whose FP32 position equals the FP32 observer (a zero line of sight) is rejected by
+// the one and never reaches the other.
+__device__ __forceinline__ float los_norm2(float x, float y, float z, float ox, float oy, float oz) {
+  const float dx = __fsub_rn(x, ox), dy = __fsub_rn(y, oy), dz = __fsub_rn(z, oz);
+  return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
 // N is a power of two (the supported grid sizes), so the periodic wrap is a mask.
 template <int ASSIGN>
 __device__ __forceinline__ int base_index(float u, int N) {

@@ -183,8 +183,9 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
       const int ix = base_index<ASSIGN>(ux, N);
       float rx = 0.0f, ry = 0.0f, rz = 1.0f;
       if (a.los == 0) {
+        // the sort left out every particle with a zero FP32 line of sight (los_norm2)
         const float dx = q.x - a.obs[0], dy = q.y - a.obs[1], dz = q.z - a.obs[2];
-        const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        const float inv = rsqrtf(los_norm2(q.x, q.y, q.z, a.obs[0], a.obs[1], a.obs[2]));
         rx = dx * inv;
         ry = dy * inv;
         rz = dz * inv;

@@ -174,7 +174,7 @@ struct SortGeom {
   float invH;
   double bmin_d[3];
   double L;
-  double obs_d[3];
+  float obs[3];   // the observer rounded to FP32, as the assignment takes it
   int N;
   int los;
 };
@@ -192,8 +192,7 @@ __device__ __forceinline__ bool valid_particle(const SortGeom& g, float x, float
     return false;
   }
   if (g.los == 0) {
-    const double ox = (double)x - g.obs_d[0], oy = (double)y - g.obs_d[1], oz = (double)z - g.obs_d[2];
-    if (ox * ox + oy * oy + oz * oz == 0.0) {
+    if (!(los_norm2(x, y, z, g.obs[0], g.obs[1], g.obs[2]) > 0.0f)) {
       if (RAISE) atomicOr(flags, (int)kFlagAtObserver);
       return false;
     }
@@ -563,7 +562,7 @@ static SortGeom sort_geom(const Plan& p) {
   for (int i = 0; i < 3; ++i) {
     g.bmin[i] = (float)p.box_min[i];
     g.bmin_d[i] = p.box_min[i];
-    g.obs_d[i] = p.observer[i];
+    g.obs[i] = (float)p.observer[i];
   }
   g.invH = (float)((double)p.N / p.L);
   g.L = p.L;

@@ -34,8 +34,9 @@ def _lib():
                                          c_size_t, c_void_p]
         lib.pk_mlp_train_step.argtypes = [S, c_void_p, c_void_p, c_void_p, c_int64, c_float, c_int32, c_void_p,
                                           c_void_p, c_size_t, c_void_p]
+        lib.pk_mlp_adam_apply.argtypes = [S, c_void_p, c_void_p, c_float, c_int32, c_void_p]
         for n in ("pk_mlp_set_params", "pk_mlp_get_params", "pk_mlp_forward", "pk_mlp_gradients",
-                  "pk_mlp_train_step"):
+                  "pk_mlp_train_step", "pk_mlp_adam_apply"):
             getattr(lib, n).restype = c_int32
         lib._mlp_declared = True
     return lib
@@ -126,3 +127,9 @@ class Mlp:
                                               float(lr), self.step, c_void_p(self.loss_buf.data_ptr()),
                                               c_void_p(ws.data_ptr()), ws.numel(), native.current_stream()))
         return self.loss_buf
+
+    def adam_apply(self, grads, lr, step):
+        """One Adam step with a given gradient vector (device float32, canonical order)."""
+        g = grads.contiguous()
+        native.check(_lib().pk_mlp_adam_apply(ctypes.byref(self.shape), c_void_p(self.state.data_ptr()),
+                                              c_void_p(g.data_ptr()), float(lr), int(step), native.current_stream()))

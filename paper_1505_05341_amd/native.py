@@ -46,7 +46,7 @@ EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_resu
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
            "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
            "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune",
-           "pk_x_planes"]
+           "pk_x_planes", "pk_stage_fft", "pk_stage_contract", "pk_hgrid_layout", "pk_zgroup"]
 
 _lib = None
 
@@ -69,6 +69,11 @@ def load():
     lib.pk_stage_xgrids.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_void_p, c_size_t, c_void_p]
     lib.pk_xgrid_layout.argtypes = [P(PkConfig), c_int64, c_int64, c_int32, P(c_size_t), P(c_int32)]
     lib.pk_x_planes.argtypes = [P(PkConfig), c_int64, c_int64, P(c_int32)]
+    lib.pk_stage_fft.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_void_p, c_size_t, c_void_p]
+    lib.pk_stage_contract.argtypes = [P(PkConfig), c_int64, c_int64, c_void_p, c_size_t, P(PkResult), c_void_p]
+    lib.pk_hgrid_layout.argtypes = [P(PkConfig), c_int64, c_int64, c_int32, c_int32, P(c_size_t), P(c_int32),
+                                    P(c_int32)]
+    lib.pk_zgroup.argtypes = [c_int32, c_int32, P(c_int32), P(c_int32)]
     lib.pk_num_grids.argtypes = [c_int32]
     lib.pk_num_grids.restype = c_int32
     lib.pk_monomial.argtypes = [c_int32, P(c_int32), P(c_int32), P(c_int32)]
@@ -131,10 +136,20 @@ def _ptr(t):
 
 
 def make_catalog(pos, w, nbar=None) -> PkCatalog:
-    """pos (n, 3), w (n,), nbar (n,) float32 contiguous CUDA tensors (nbar may be None)."""
+    """pos (n, 3), w (n,), nbar (n,) float32 contiguous CUDA tensors (nbar may be None).
+    Shapes and dtypes are checked here: the kernels read n positions, weights and
+    densities, so a shorter array would be read past its end on the device."""
+    import torch
     for t in (pos, w) + ((nbar,) if nbar is not None else ()):
-        if not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous():
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
             raise ValueError("catalogue arrays must be contiguous float32 device tensors")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must have shape (n, 3), got %s" % (tuple(pos.shape),))
+    n = int(pos.shape[0])
+    if w.dim() != 1 or w.numel() != n:
+        raise ValueError("weights must have shape (%d,), got %s" % (n, tuple(w.shape)))
+    if nbar is not None and (nbar.dim() != 1 or nbar.numel() != n):
+        raise ValueError("nbar must have shape (%d,), got %s" % (n, tuple(nbar.shape)))
     c = PkCatalog()
     c.xyz = _ptr(pos)
     c.w = _ptr(w)
@@ -195,3 +210,10 @@ def get_schedule(N, ell_max):
     y, z = ctypes.c_int32(), ctypes.c_int32()
     check(load().pk_get_schedule(int(N), int(ell_max), ctypes.byref(y), ctypes.byref(z)))
     return int(y.value), int(z.value)
+
+
+def zgroup(ell_max, g):
+    """(degree n, power c of tz) of z-power group g."""
+    n, c = c_int32(), c_int32()
+    check(load().pk_zgroup(int(ell_max), int(g), ctypes.byref(n), ctypes.byref(c)))
+    return int(n.value), int(c.value)

@@ -32,10 +32,10 @@ def test_correction_beats_raw_coarse_on_held_out_mocks(trained):
     correction, model, _, test, _ = trained
     err = correction.errors_vs_fine(test["meta"], model.predict(test["X"]))
     print("held-out |P - P_fine| / R:", err)
-    # monopole and quadrupole improve on average; the hexadecapole may not get worse much
+    # every multipole improves on average (the hexadecapole at least does not get worse)
     assert err["corrected_mean"][0] < 0.7 * err["raw_mean"][0]
     assert err["corrected_mean"][1] < err["raw_mean"][1]
-    assert err["corrected_mean"][2] < 1.2 * err["raw_mean"][2]
+    assert err["corrected_mean"][2] <= err["raw_mean"][2]
 
 
 def test_out_of_domain_falls_back_to_fine_grid(trained):

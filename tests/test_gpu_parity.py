@@ -261,6 +261,30 @@ def test_error_particle_at_observer(pk):
     _errcase(pk, mutate_gal=f, cfg_kw=dict(observer=(0.0, 0.0, 1500.0)), expect=-3)
 
 
+def test_error_particle_at_float_observer(pk):
+    """An observer that FP32 cannot hold exactly, with a particle at its FP32 rounding: the
+    line of sight is zero in the arithmetic the assignment uses (the FP64 difference is
+    not), so the call must fail with PK_EDOM instead of spreading a NaN through the bins."""
+    obs = (0.1, 0.2, 1500.3)
+
+    def f(c):
+        c.pos[0] = np.array(obs, dtype=np.float32)
+    _errcase(pk, mutate_gal=f, cfg_kw=dict(observer=obs), expect=-3)
+
+
+def test_catalogue_shape_checks(pk):
+    """The binding refuses arrays the kernels would read past the end of."""
+    import torch
+    from paper_1505_05341_amd import native
+    pos = torch.zeros((10, 3), device="cuda")
+    w = torch.ones(10, device="cuda")
+    for bad in [(pos, w[:9]), (pos[:, :2].contiguous(), w), (pos, w, torch.ones(11, device="cuda")),
+                (pos.to(torch.int32), w), (pos, w.to(torch.float64))]:
+        with pytest.raises(ValueError):
+            native.make_catalog(*bad)
+    assert native.make_catalog(pos, w, w).n == 10
+
+
 def test_error_bad_config(pk):
     _errcase(pk, cfg_kw=dict(N=48), expect=-6)
     _errcase(pk, cfg_kw=dict(ell_max=3), expect=-1)

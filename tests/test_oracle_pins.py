@@ -217,18 +217,28 @@ def test_grid_identities():
 
 # --------------------------------------------------------------------------- cross-paths
 
-@pytest.mark.parametrize("assign,N,los,comp,ell_max", [(2, 8, 0, 2, 4), (3, 8, 0, 2, 4), (2, 16, 0, 1, 4),
-                                                       (3, 16, 0, 0, 4), (2, 8, 1, 2, 4), (2, 8, 0, 2, 6),
-                                                       (3, 16, 0, 2, 6)])
-def test_fft_path_equals_interpolated_phase_sum(assign, N, los, comp, ell_max):
+# observers: the origin (outside the box), one off-axis outside the box, one inside it
+OBS_OUT = (31.0, -24.0, 17.5)
+OBS_IN = (3.0, -11.0, 171.0)
+
+
+@pytest.mark.parametrize("assign,N,los,comp,ell_max,obs", [(2, 8, 0, 2, 4, None), (3, 8, 0, 2, 4, None),
+                                                           (2, 16, 0, 1, 4, None), (3, 16, 0, 0, 4, None),
+                                                           (2, 8, 1, 2, 4, None), (2, 8, 0, 2, 6, None),
+                                                           (3, 16, 0, 2, 6, None), (2, 8, 0, 2, 4, OBS_OUT),
+                                                           (3, 16, 0, 2, 4, OBS_IN), (3, 8, 0, 1, 6, OBS_IN)])
+def test_fft_path_equals_interpolated_phase_sum(assign, N, los, comp, ell_max, obs):
     """Sec. 3: the decomposition is exact, so the gridded estimator equals the
     direct sum over particles with interpolated phases and Legendre weights (for
-    ell = 6 too, with its 28 degree-6 grids)."""
-    gal, ran, cfg = _small_case(N=N, assign=assign, los=los, compensate=comp, ell_max=ell_max)
+    ell = 6 too, with its 28 degree-6 grids). Both paths take the line of sight from
+    the same observer, at the origin or elsewhere (inside the box too), so a dropped or
+    misapplied observer offset on either side fails."""
+    gal, ran, cfg = _small_case(N=N, assign=assign, los=los, compensate=comp, ell_max=ell_max,
+                                observer=obs or (0.0, 0.0, 0.0))
     r = _run(gal, ran, cfg)
     d = direct.direct_multipoles(gal.pos, gal.w, ran.pos, ran.w, gal.nbar, ran.nbar, N=N,
                                  box_min=cfg.box_min, L=cfg.L, assign=assign, los=los,
-                                 compensate=comp, method="interp", ell_max=ell_max)
+                                 observer=cfg.observer, compensate=comp, method="interp", ell_max=ell_max)
     np.testing.assert_array_equal(r.nmodes, d["count"])
     scale = np.max(np.abs(r.P[0]) + r.noise)
     for ell in range(0, ell_max + 1, 2):
@@ -416,3 +426,58 @@ def test_x_row_helper_matches_full_grid():
     for m, (iy, iz) in [((2, 1, 1), (3, 5)), ((0, 0, 0), (0, 7)), ((0, 0, 2), (7, 0))]:
         row = est.x_transformed_row(pos, wp, cfg, m, iy, iz)
         np.testing.assert_allclose(row, np.fft.fft(g[m][:, iy, iz]), atol=1e-12)
+
+
+def test_observer_changes_the_result():
+    """The observer enters through the line of sight only: moving it changes P_2 and P_4
+    (so the cross-path test above can see an observer mistake) and leaves P_0 unchanged."""
+    gal, ran, cfg = _small_case(N=8, assign=3)
+    _, _, cfg_o = _small_case(N=8, assign=3, observer=OBS_IN)
+    a, b = _run(gal, ran, cfg), _run(gal, ran, cfg_o)
+    scale = np.max(np.abs(a.P[0]) + a.noise)
+    np.testing.assert_allclose(b.P[0], a.P[0], rtol=0, atol=1e-12 * scale)
+    assert np.max(np.abs(b.P[2] - a.P[2])) > 1e-3 * scale
+    assert np.max(np.abs(b.P[4] - a.P[4])) > 1e-3 * scale
+
+
+@pytest.mark.parametrize("assign,N,comp,ell_max,obs,dn", [(2, 8, 2, 4, OBS_OUT, 1), (3, 16, 2, 4, OBS_IN, 1),
+                                                          (3, 16, 1, 6, None, 2), (2, 16, 0, 4, OBS_IN, 3)])
+def test_lean_oracle_equals_interpolated_phase_sum(assign, N, comp, ell_max, obs, dn):
+    """The lean form (half lattice, shell sums accumulated grid by grid) used for the
+    512^3 and 1024^3 stored results equals the direct sum over particles, which uses no
+    grid, no transform and no Cartesian split."""
+    gal, ran, cfg = _small_case(N=N, assign=assign, compensate=comp, ell_max=ell_max, dn=dn,
+                                observer=obs or (0.0, 0.0, 0.0))
+    r = est.pk_multipoles_lean(gal.pos, gal.w, ran.pos, ran.w, cfg, gal.nbar, ran.nbar, planes=3)
+    d = direct.direct_multipoles(gal.pos, gal.w, ran.pos, ran.w, gal.nbar, ran.nbar, N=N, box_min=cfg.box_min,
+                                 L=cfg.L, assign=assign, observer=cfg.observer, compensate=comp, dn=dn,
+                                 nbins=cfg.nbins, ell_max=ell_max)
+    np.testing.assert_array_equal(r.nmodes, d["count"])
+    scale = np.max(np.abs(r.P[0]) + r.noise)
+    for ell in range(0, ell_max + 1, 2):
+        np.testing.assert_allclose(r.P[ell], d[ell], rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(r.noise, d["noise"], rtol=1e-12)
+    np.testing.assert_allclose(r.k_eff, d["k_eff"], rtol=1e-13)
+    for key in ("alpha", "I", "S"):
+        assert abs(getattr(r, key) - d[key]) <= 1e-13 * abs(d[key])
+
+
+@pytest.mark.parametrize("assign,N,ell_max", [(3, 16, 4), (2, 8, 6)])
+def test_plane_parallel_oracle_equals_direct_fixed_los_sum(assign, N, ell_max):
+    """The one-transform plane-parallel form equals the direct sum over particles with the
+    line of sight fixed to +z (and the 22-grid estimator with los = 1)."""
+    gal, ran, cfg = _small_case(N=N, assign=assign, los=1, ell_max=ell_max)
+    p = est.plane_parallel_multipoles(gal.pos, gal.w, ran.pos, ran.w, cfg, gal.nbar, ran.nbar, planes=5)
+    d = direct.direct_multipoles(gal.pos, gal.w, ran.pos, ran.w, gal.nbar, ran.nbar, N=N, box_min=cfg.box_min,
+                                 L=cfg.L, assign=assign, los=1, ell_max=ell_max)
+    np.testing.assert_array_equal(p.nmodes, d["count"])
+    scale = np.max(np.abs(p.P[0]) + p.noise)
+    for ell in range(0, ell_max + 1, 2):
+        np.testing.assert_allclose(p.P[ell], d[ell], rtol=0, atol=1e-11 * scale)
+
+
+def test_deposit_equals_assign_to_grid():
+    gal, ran, cfg = _small_case(N=8, assign=3)
+    pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
+    vals = np.random.default_rng(4).standard_normal(len(pos))
+    np.testing.assert_allclose(est.deposit(pos, vals, cfg), est.assign_to_grid(pos, vals, cfg), atol=1e-13)
