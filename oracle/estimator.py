@@ -414,16 +414,23 @@ def x_transformed_row(pos, wprime, cfg: Config, m, iy, iz):
 
 def deposit(pos, values, cfg: Config):
     """The same periodic CIC/TSC deposit as assign_to_grid, with the cells and weights of
-    every stencil offset gathered first and summed by one bincount over the grid (for
+    several stencil offsets gathered first and summed by one bincount over the grid (for
     catalogues far smaller than the grid, where a dense bincount of N^3 bins per stencil
-    offset would dominate the cost)."""
+    offset would dominate the cost; the gathered lists are kept to about N^3 entries)."""
     N = cfg.N
     u = grid_units(pos, cfg.box_min, cfg.L, N)
     values = np.asarray(values, dtype=np.float64)
     ix, ox, wx = axis_weights(u[:, 0], cfg.assign)
     iy, oy, wy = axis_weights(u[:, 1], cfg.assign)
     iz, oz, wz = axis_weights(u[:, 2], cfg.assign)
+    g = np.zeros(N * N * N, dtype=np.float64)
     cells, weights = [], []
+
+    def flush():
+        if cells:
+            g[:] += np.bincount(np.concatenate(cells), weights=np.concatenate(weights), minlength=N * N * N)
+            cells.clear()
+            weights.clear()
     for a, dx in enumerate(ox):
         cx = (ix + dx) % N
         for b, dy in enumerate(oy):
@@ -433,7 +440,9 @@ def deposit(pos, values, cfg: Config):
                 cz = (iz + dz) % N
                 cells.append((cx * N + cy) * N + cz)
                 weights.append(values * wxy * wz[c])
-    g = np.bincount(np.concatenate(cells), weights=np.concatenate(weights), minlength=N * N * N)
+                if len(cells) * len(values) >= N * N * N:
+                    flush()
+    flush()
     return g.reshape(N, N, N)
 
 
@@ -489,8 +498,13 @@ def _half_spectrum(grid, workers):
     return sfft.rfftn(grid, workers=workers)[:, :, :N // 2]
 
 
+def _workers(workers):
+    """Threads of the library FFT: at most 16 (a one-GPU share of a host's cores)."""
+    return workers or max(1, min(16, os.cpu_count() or 1))
+
+
 def pk_multipoles_lean(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=None, ran_nbar=None,
-                       workers=None, planes=16, log=None):
+                       workers=None, planes=16, log=None, max_grids=None):
     """Same result as pk_multipoles, in the memory of about two transformed grids.
 
     Two facts of the same definition make it lean; the steps are otherwise those of
@@ -504,9 +518,12 @@ def pk_multipoles_lean(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=Non
       * Re[A_0 A_n^*] = sum_{|m| = n} c_m khat^m Re[A_0 G_m^*] (Eqs. 10, 12; khat^m is real)
         is linear in the grids, so the shell sums of Q_n are accumulated grid by grid
         and only A_0 (at the binned modes) and the current G_m are held.
+
+    log(message), if given, is called after the set-up and after each grid; max_grids, if
+    given, stops after that many grids (an incomplete result, for timing a sample only).
     """
     assert cfg.nbins * cfg.dn <= cfg.N // 2, "bins must stay below the Nyquist frequency"
-    workers = workers or (os.cpu_count() or 1)
+    workers = _workers(workers)
     alpha, I, S = catalogue_scalars(gal_w, ran_w, gal_nbar, ran_nbar, cfg.norm_from)
     pos = np.concatenate([np.asarray(gal_pos, np.float64), np.asarray(ran_pos, np.float64)])
     wprime = signed_weights(gal_w, ran_w, alpha)
@@ -517,7 +534,11 @@ def pk_multipoles_lean(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_nbar=Non
     for n in range(0, cfg.ell_max + 1, 2):
         sums[f"Q{n}"] = np.zeros(nb)
     a0 = []
-    for (a, b, c), coef in los_monomials(cfg.ell_max):
+    if log:
+        log("set-up done")
+    for i, ((a, b, c), coef) in enumerate(los_monomials(cfg.ell_max)):
+        if max_grids is not None and i >= max_grids:
+            break
         n = a + b + c
         vals = wprime * rh[:, 0] ** a * rh[:, 1] ** b * rh[:, 2] ** c
         Gm = _half_spectrum(deposit(pos, vals, cfg), workers)
@@ -552,7 +573,7 @@ def plane_parallel_multipoles(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_n
     pk_multipoles_lean."""
     from . import direct
     assert cfg.nbins * cfg.dn <= cfg.N // 2, "bins must stay below the Nyquist frequency"
-    workers = workers or (os.cpu_count() or 1)
+    workers = _workers(workers)
     alpha, I, S = catalogue_scalars(gal_w, ran_w, gal_nbar, ran_nbar, cfg.norm_from)
     pos = np.concatenate([np.asarray(gal_pos, np.float64), np.asarray(ran_pos, np.float64)])
     wprime = signed_weights(gal_w, ran_w, alpha)
@@ -576,3 +597,27 @@ def plane_parallel_multipoles(gal_pos, gal_w, ran_pos, ran_w, cfg: Config, gal_n
     P = {ell: np.where(ok, qs[ell] / den - (noise if ell == 0 else 0.0), 0.0) for ell in ells}
     k_eff = np.where(ok, (2.0 * np.pi / cfg.L) * ks / np.where(ok, cnt, 1.0), 0.0)
     return Result(k_eff=k_eff, nmodes=cnt.astype(np.int64), P=P, noise=noise, alpha=alpha, I=I, S=S)
+
+
+def xy_transformed_column(pos, wprime, cfg: Config, m, kx, ky):
+    """The transform along x and y of every plane z of grid m at the mode (kx, ky):
+    sum over cells (x, y) of g_m(x, y, z) e^{-2 pi i (kx x + ky y) / N} (unnormalised, the
+    sign of fft3), for z = 0 .. N-1, accumulated from each particle's deposits (no grid is
+    formed). The weight a particle puts on its cells factorises by axis, so the sum over
+    its stencil's (x, y) cells is the product of its two one-axis phase sums."""
+    N = cfg.N
+    u = grid_units(pos, cfg.box_min, cfg.L, N)
+    ix, ox, wx = axis_weights(u[:, 0], cfg.assign)
+    iy, oy, wy = axis_weights(u[:, 1], cfg.assign)
+    iz, oz, wz = axis_weights(u[:, 2], cfg.assign)
+    rh = unit_los(pos, cfg.observer, cfg.los)
+    a, b, c = m
+    vals = np.asarray(wprime, np.float64) * rh[:, 0] ** a * rh[:, 1] ** b * rh[:, 2] ** c
+    px = sum(wx[j] * np.exp(-2j * np.pi * kx * ((ix + d) % N) / N) for j, d in enumerate(ox))
+    py = sum(wy[j] * np.exp(-2j * np.pi * ky * ((iy + d) % N) / N) for j, d in enumerate(oy))
+    col = np.zeros(N, dtype=np.complex128)
+    for j, d in enumerate(oz):
+        cz = (iz + d) % N
+        v = vals * px * py * wz[j]
+        col += np.bincount(cz, weights=v.real, minlength=N) + 1j * np.bincount(cz, weights=v.imag, minlength=N)
+    return col

