@@ -134,6 +134,25 @@ pk_status pk_workspace_size(const pk_config* cfg, int64_t n_gal, int64_t n_ran, 
 pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
                         void* workspace, size_t workspace_bytes, pk_result* out, void* hip_stream);
 
+/* Bytes of the fixed scratch array that pk_multipoles_noalloc works in (64 MiB). */
+#define PK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code being captured into a HIP graph,
+ * tight serving loops, harnesses that forbid allocation): pk_multipoles with its
+ * workspace replaced by a fixed array of PK_NOALLOC_SCRATCH_BYTES in the library's device
+ * image (each GPU the library runs on holds its own copy from the first launch of any
+ * libpk kernel until the process ends). The call allocates nothing: no hipMalloc, no
+ * stream or event creation, no second stream for slabs; the result is staged in a
+ * per-thread host buffer. Same inputs, outputs, synchronous behaviour and errors as
+ * pk_multipoles, plus PK_EWORKSPACE when the configuration and catalogue sizes need more
+ * scratch than the array holds (pk_workspace_size() > PK_NOALLOC_SCRATCH_BYTES, e.g. a
+ * 64^3 grid with about 1e6 particles fits, a 256^3 grid does not) or more than 1024
+ * result values. All calls on one GPU share its array: calls that overlap in time on
+ * one GPU (several host threads or streams) race and give wrong results; serialise them.
+ * Every part of the array a call reads is written by that call first. */
+pk_status pk_multipoles_noalloc(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
+                                pk_result* out, void* hip_stream);
+
 /* Asynchronous form: queues the same work and leaves the results in device memory at
  * `d_result` (float64, pk_result_doubles(cfg) values: k_eff[nbins], P[(ell_max/2+1) nbins],
  * noise[nbins], nmodes[nbins] (as doubles), wedges[2 nbins], then alpha, I, S and the

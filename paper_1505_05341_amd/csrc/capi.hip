@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -434,6 +435,62 @@ pk_status pk_multipoles(const pk_config* cfg, const pk_catalog* gal, const pk_ca
   st = run_stages(p, *gal, *ran, ws, d_res, s, Stop::kNone);
   if (st != PK_OK) return st;
   return fetch_result(p, d_res, s, out);
+}
+
+// --------------------------------------------------- entry point that allocates nothing
+// For callers that cannot allocate (code being captured into a graph, serving loops,
+// harnesses that forbid allocation): the workspace is a fixed array in the library's
+// device image. Each GPU holds its own copy of it from the first launch of any of the
+// library's kernels until the process ends. In host code the array's name is only a
+// stand-in; its device address, which differs per GPU, is taken once per device with
+// hipGetSymbolAddress and used everywhere instead of the name.
+constexpr size_t kScratchBytes = PK_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchResultMax = 1024;  // doubles of the result staging buffer
+static __device__ __align__(256) char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static char* g_scratch_dev[kMaxDevices];
+
+static pk_status scratch_for_device(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "get device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(PK_EDEVICE, "device index beyond the library's per-device table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "address of the scratch array");
+    if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(PK_EDEVICE, "scratch array missing or misaligned");
+    g_scratch_dev[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return PK_OK;
+}
+
+pk_status pk_multipoles_noalloc(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran, pk_result* out,
+                                void* hip_stream) {
+  Plan p;
+  pk_status st = prepare_plan(cfg, gal, ran, &p);
+  if (st != PK_OK) return st;
+  if (!out) return fail(PK_EINVAL, "null result");
+  if (p.total > kScratchBytes)
+    return fail(PK_EWORKSPACE, "this configuration needs " + std::to_string(p.total) +
+                                   " bytes of scratch; pk_multipoles_noalloc holds " +
+                                   std::to_string(kScratchBytes) + " (use pk_multipoles with a workspace)");
+  if (p.result_doubles > kScratchResultMax)
+    return fail(PK_EWORKSPACE, "too many bins for pk_multipoles_noalloc's result buffer");
+  char* ws = nullptr;
+  if ((st = scratch_for_device(&ws)) != PK_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* d_res = at<double>(ws, p.off_result);
+  // one stream only (no second stream for slabs) and no timing events: nothing is created
+  st = run_stages(p, *gal, *ran, ws, d_res, s, Stop::kNone, /*one_stream=*/true);
+  if (st != PK_OK) return st;
+  static thread_local double h[kScratchResultMax];
+  hipError_t e = hipMemcpyAsync(h, d_res, sizeof(double) * (size_t)p.result_doubles, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "result copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream synchronize");
+  return unpack_result(h, p.nbins, p.ell_max / 2 + 1, out);
 }
 
 // ------------------------------------------------------------------- FFT schedules
