@@ -208,10 +208,29 @@ def run_batch(args):
         for l in (0, 2, 4):
             worst = max(worst, float(np.max(np.abs(a["P%d" % l][ok] - b["P%d" % l][ok]) / raw)))
     best = min(times)
+    # host cost per mock of the batch (graph capture, update, launch): the same call on tiny
+    # mocks (32^3, 3,000 particles), whose kernels take a few microseconds each
+    from paper_1505_05341_amd import catalogs
+    tg, tr, tc = catalogs.tiny_plain(n_gal=300, n_ran=3000)
+    tg, tr = pk.DeviceCatalog.from_host(tg), pk.DeviceCatalog.from_host(tr)
+    ntiny = 256
+    pk.pk_multipoles_batch([tg] * ntiny, [tr] * ntiny, [tc] * ntiny, lanes=args.lanes, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk.pk_multipoles_batch([tg] * ntiny, [tr] * ntiny, [tc] * ntiny, lanes=args.lanes, workspace=ws)
+    torch.cuda.synchronize()
+    host_ms = 1e3 * (time.perf_counter() - t0) / ntiny
+    t0 = time.perf_counter()
+    for _ in range(ntiny):
+        pk.pk_multipoles(tg, tr, tc, ws1)
+    torch.cuda.synchronize()
+    single_tiny_ms = 1e3 * (time.perf_counter() - t0) / ntiny
+    log("tiny mocks: %.3f ms per mock in a batch, %.3f ms per single call" % (host_ms, single_tiny_ms))
     out = {"metric": "P0/P2/P4 mocks/sec, batched ensemble", "value": len(cfgs) / best, "unit": "mocks/s",
            "n_gpus": 1, "steps": args.steps, "ms_per_batch": best * 1e3, "mocks": len(cfgs),
            "lanes": args.lanes, "sequential_mocks_per_s": len(cfgs) / t_seq,
            "batch_vs_sequential_max_rel_diff": worst, "particles": npart, "dtype": "f32", "data": "synthetic",
+           "tiny_mock_ms_per_mock_batched": host_ms, "tiny_mock_ms_per_single_call": single_tiny_ms,
            "config": {"workload": batch_workload.__doc__.split("\n")[0].strip()}}
     print(json.dumps(out), flush=True)
 

@@ -92,6 +92,31 @@ def _fft_workers():
     return max(1, min(16, os.cpu_count() or 1))
 
 
+def lognormal_spectra(N_field, L, amp=2.0e4, k0=0.1, slope=-1.5):
+    """The spectra of the lognormal recipe on its field grid (rfft half grid, modes of the
+    periodic box of side L): the target galaxy power P(k) = amp (k/k0)^slope (P(0) = 0),
+    and the power P_G of the Gaussian field G with xi_G = ln(1 + xi) (negative values
+    clipped, P_G(0) = 0). Returns (|k|, P, P_G, sigma_G^2), each (N, N, N/2 + 1)."""
+    import scipy.fft as sfft
+
+    N = int(N_field)
+    H = L / N
+    wk = _fft_workers()
+    kx = 2.0 * np.pi * np.fft.fftfreq(N, d=H)
+    kz = 2.0 * np.pi * np.fft.rfftfreq(N, d=H)
+    kmag = np.sqrt(kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2)
+    with np.errstate(divide="ignore"):
+        Pk = np.where(kmag > 0, amp * (kmag / k0) ** slope, 0.0)
+    # xi(r) = (1/V) sum_k P(k) e^{ik.r}; irfftn carries 1/N^3
+    xig = np.log1p(sfft.irfftn(Pk, s=(N, N, N), workers=wk) * (N ** 3 / L ** 3))
+    PG = np.real(sfft.rfftn(xig, workers=wk)) * (L ** 3 / N ** 3)
+    sigma2 = float(xig[0, 0, 0])
+    del xig
+    np.maximum(PG, 0.0, out=PG)
+    PG[0, 0, 0] = 0.0
+    return kmag, Pk, PG, sigma2
+
+
 def lognormal_rsd(*, N_field, L, center, nbar, seed, amp=2.0e4, k0=0.1, slope=-1.5,
                   f=0.75, b=2.0, ran_factor=20.0, P_fkp=1.0e4, observer=(0.0, 0.0, 0.0)):
     """Lognormal RSD mock in a periodic cube of side L centred at `center`.
@@ -112,20 +137,9 @@ def lognormal_rsd(*, N_field, L, center, nbar, seed, amp=2.0e4, k0=0.1, slope=-1
     wk = _fft_workers()
     kx = 2.0 * np.pi * np.fft.fftfreq(N, d=H)
     kz = 2.0 * np.pi * np.fft.rfftfreq(N, d=H)
-    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
-    kmag = np.sqrt(k2)
-    with np.errstate(divide="ignore"):
-        Pk = np.where(kmag > 0, amp * (kmag / k0) ** slope, 0.0)
-    # xi(r) = (1/V) sum_k P(k) e^{ik.r}; irfftn carries 1/N^3
-    xi = sfft.irfftn(Pk, s=(N, N, N), workers=wk) * (N ** 3 / L ** 3)
+    kmag, Pk, PG, sigma2 = lognormal_spectra(N, L, amp, k0, slope)
     del Pk
-    xig = np.log1p(xi)
-    del xi
-    PG = np.real(sfft.rfftn(xig, workers=wk)) * (L ** 3 / N ** 3)
-    sigma2 = float(xig[0, 0, 0])
-    del xig
-    np.maximum(PG, 0.0, out=PG)
-    PG[0, 0, 0] = 0.0
+    k2 = kmag * kmag
     white = rng.standard_normal((N, N, N))
     Gk = sfft.rfftn(white, workers=wk)
     del white

@@ -41,27 +41,32 @@ struct XArgs {
   int64_t grid_stride;  // float2 elements per grid of X: xr * xs * N * Kx
 };
 
-// Block geometry: 512 threads and chunks of 1024 particles up to N = 512; from N = 1024 on,
-// blocks of 1024 threads (one cell per thread at 1024, two at 2048) and chunks of 2048.
-template <int N>
+// Block geometry: 512 threads up to N = 512; from N = 1024 on, blocks of 1024 threads (one
+// cell per thread at 1024, two at 2048). Particles per LDS chunk: 3 per thread for CIC at
+// 512 and TSC at 1024, where the chunk area then still fits beside the transformed rows for
+// 4 (512) or 2 (1024) blocks per CU and the records held through the counting sort fit the
+// register budget (fewer chunk rounds per row, each with its barriers: 4.75 -> 4.46 ms at
+// 512^3 CIC, 66.8 -> 61.7 ms at 1024^3 TSC; 4 per thread was slower at 512; TSC at 512 and
+// CIC at 1024 would spill), 2 elsewhere.
+template <int N, int ASSIGN>
 struct XGeom {
-  static constexpr int NT = N >= 1024 ? 1024 : 512;      // threads
-  static constexpr int CHUNK = N >= 1024 ? 2048 : 1024;  // particles per LDS chunk
-  static constexpr int PER = CHUNK / NT;                  // particles per thread per chunk
+  static constexpr int NT = N >= 1024 ? 1024 : 512;  // threads
+  static constexpr int PER = ((N == 512 && ASSIGN == PK_CIC) || (N == 1024 && ASSIGN == PK_TSC)) ? 3 : 2;
+  static constexpr int CHUNK = NT * PER;              // particles per LDS chunk
 };
 
 // Bytes of the gather-phase LDS area: the chunk's particles in base-cell order, pa
 // float4[XCHUNK] (fx, w' W_y W_z, rx, ry) and pr float[XCHUNK] (rz); cnt uint32[N] (counts)
 // and st uint32[N + 1] (first particle of each cell).
-template <int N>
+template <int N, int ASSIGN>
 constexpr size_t gather_lds_bytes() {
-  return (size_t)XGeom<N>::CHUNK * (16 + 4) + (size_t)N * 4 + (size_t)(N + 1) * 4;
+  return (size_t)XGeom<N, ASSIGN>::CHUNK * (16 + 4) + (size_t)N * 4 + (size_t)(N + 1) * 4;
 }
 
 // Exclusive scan of cnt[0, N) into st[0, N] (st[N] = total); cnt[i] = st[i] on exit.
 template <int N>
 __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
-  constexpr int NT = XGeom<N>::NT;
+  constexpr int NT = XGeom<N, PK_CIC>::NT;
   constexpr int PER = (N + NT - 1) / NT;
   __shared__ uint32_t wsum[NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -121,7 +126,8 @@ template <int N, int ASSIGN, int NG, int NP, int S = (ASSIGN == PK_CIC ? 2 : 3)>
 __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict__ sorted, const uint32_t (&beg)[S * S],
                                             const uint32_t (&pre)[S * S + 1], const XArgs& a) {
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
-  constexpr int NT = XGeom<N>::NT, XCHUNK = XGeom<N>::CHUNK, XPER = XGeom<N>::PER;
+  using XG = XGeom<N, ASSIGN>;
+  constexpr int NT = XG::NT, XCHUNK = XG::CHUNK, XPER = XG::PER;
   constexpr int CPT = (N + NT - 1) / NT;  // target cells per thread
   char* base = reinterpret_cast<char*>(lds);
   float4* pa = reinterpret_cast<float4*>(base);
@@ -275,15 +281,15 @@ constexpr int xpass_waves() { return (N >= 2048 || ELL >= 6) ? 4 : 8; }
 
 // Bytes before the x pass's LDS twiddle table: the larger of the gather area and the
 // 2 NP transformed rows (which alias each other).
-template <int N, int NP>
+template <int N, int ASSIGN, int NP>
 constexpr size_t xpass_tw_offset() {
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
-  const size_t g = gather_lds_bytes<N>();
+  const size_t g = gather_lds_bytes<N, ASSIGN>();
   return ((rows > g ? rows : g) + 15) / 16 * 16;
 }
 
 template <int N, int ASSIGN, int ELL>
-__global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
+__global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
   constexpr int GK = kept_count(ELL);   // gathered and transformed rows
   constexpr int ND = dep_count(ELL);    // rows written as their combinations
@@ -291,7 +297,7 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
   constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
   using F = Fft<N>;
-  static_assert(NP * F::T <= XGeom<N>::NT, "row pairs do not fit the block");
+  static_assert(NP * F::T <= XGeom<N, ASSIGN>::NT, "row pairs do not fit the block");
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   // first thread index of this wave, a scalar: the output stage forms its kx from it and
@@ -320,8 +326,8 @@ __global__ __launch_bounds__(XGeom<N>::NT) __attribute__((amdgpu_waves_per_eu(xp
     pre[s + 1] = __builtin_amdgcn_readfirstlane(pre[s] + (end > beg[s] ? end - beg[s] : 0u));
   }
   // the twiddles of the x transform in LDS (the barriers of the gather make them visible)
-  float2* twl = reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + xpass_tw_offset<N, NP>());
-  for (int i = tid; i < N; i += XGeom<N>::NT) twl[i] = tw[i];
+  float2* twl = reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + xpass_tw_offset<N, ASSIGN, NP>());
+  for (int i = tid; i < N; i += XGeom<N, ASSIGN>::NT) twl[i] = tw[i];
   gather_rows<N, ASSIGN, GK, NP>(lds, sorted, beg, pre, a);
 
   // transform along x: rows (2q, 2q+1) as the real and imaginary parts of one row
@@ -402,10 +408,10 @@ static hipError_t launch_x3(const Plan& p, char* ws, const XArgs& a, hipStream_t
   constexpr int NP = (kept_count(ELL) + 1) / 2;
   const size_t rows = (size_t)2 * NP * N * sizeof(float);
   (void)rows;
-  const size_t shmem = xpass_tw_offset<N, NP>() + (size_t)N * sizeof(float2);
+  const size_t shmem = xpass_tw_offset<N, ASSIGN, NP>() + (size_t)N * sizeof(float2);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&xpass_kernel<N, ASSIGN, ELL>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL>), dim3(N, p.xs), dim3(XGeom<N>::NT), shmem, s,
+  hipLaunchKernelGGL((xpass_kernel<N, ASSIGN, ELL>), dim3(N, p.xs), dim3(XGeom<N, ASSIGN>::NT), shmem, s,
                      at<const float4>(ws, p.off_sorted), at<const uint32_t>(ws, p.off_rowoff),
                      at<const float2>(ws, p.off_tw), at<float2>(ws, p.off_X), a);
   return hipGetLastError();
