@@ -1,8 +1,8 @@
 // Per-particle arithmetic shared by the row sort and the assignment kernels, so that
-// both derive a particle's base cell from the same FP32 operations.
+// both derive a particle's base cell from the same operations.
 //
 // Mass assignment (Sec. 4 names cloud-in-cell; the triangular-shaped cloud is the
-// next order): nodes at box_min + j H, u = (x - box_min) / H.
+// next order): nodes at box_min + j H, u = (x - box_min) / H, H = L / N.
 //   CIC: i = floor(u), f = u - i, weights (1 - f, f) on cells (i, i + 1);
 //   TSC: i = floor(u + 1/2), d = u - i, weights (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2)
 //        on cells (i - 1, i, i + 1).
@@ -14,10 +14,6 @@
 
 namespace pk {
 
-__device__ __forceinline__ float grid_coord(float x, float bmin, float invH) {
-  return __fmul_rn(__fsub_rn(x, bmin), invH);
-}
-
 // Squared distance of a particle to the observer in FP32, with the rounding of every
 // operation fixed (no contraction left to the compiler), so that the validity test of
 // the sort and the line of sight of the assignment take the same value: a particle
@@ -28,18 +24,26 @@ __device__ __forceinline__ float los_norm2(float x, float y, float z, float ox, 
   return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
 }
 
-// N is a power of two (the supported grid sizes), so the periodic wrap is a mask.
-template <int ASSIGN>
-__device__ __forceinline__ int base_index(float u, int N) {
-  const float t = ASSIGN == PK_CIC ? u : __fadd_rn(u, 0.5f);
-  return (int)floorf(t) & (N - 1);
-}
+// Cell of a coordinate along one axis: u = (x - box_min) N / L formed in FP64 from the FP32
+// position (as the FP64 oracle forms it, so both take the same cell decisions), the base
+// node i (wrapped modulo N; N is a power of two, so the wrap is a mask) and the offset
+// f = u - floor(t) in [0, 1) (CIC, t = u) or [-1/2, 1/2) (TSC, t = u + 1/2), rounded to FP32
+// only once it is small, so that it keeps FP32's relative precision at any N (u formed in
+// FP32 would put every offset off by up to |u| 2^-24, ~6e-5 of a cell at N = 1024). The cost
+// is a few FP64 vector instructions (half the FP32 rate) per particle and axis.
+struct AxisCell {
+  int i;    // base node
+  float f;  // offset from it
+};
 
-// Offset of u from its base node (f for CIC, d for TSC).
 template <int ASSIGN>
-__device__ __forceinline__ float base_offset(float u) {
-  const float t = ASSIGN == PK_CIC ? u : __fadd_rn(u, 0.5f);
-  return __fsub_rn(u, floorf(t));
+__device__ __forceinline__ AxisCell axis_cell(float x, double bmin, double invH, int N) {
+  const double u = __dmul_rn(__dsub_rn((double)x, bmin), invH);
+  const double fl = floor(ASSIGN == PK_CIC ? u : __dadd_rn(u, 0.5));
+  AxisCell c;
+  c.i = (int)fl & (N - 1);
+  c.f = (float)__dsub_rn(u, fl);
+  return c;
 }
 
 // Weight of the cell at base + o for offset o in [0, 1] (CIC) or [-1, 1] (TSC).

@@ -31,8 +31,8 @@
 namespace pk {
 
 struct XArgs {
-  float bmin[3];
-  float invH;
+  double bmin[3];
+  double invH;
   float obs[3];
   int los;
   int Kx;
@@ -190,12 +190,11 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
       if (i >= n) continue;
       const float4 q = qv[j];
       const int oy = O0 + sv[j] % S, oz = O0 + sv[j] / S;
-      const float uy = grid_coord(q.y, a.bmin[1], a.invH);
-      const float uz = grid_coord(q.z, a.bmin[2], a.invH);
-      const float ux = grid_coord(q.x, a.bmin[0], a.invH);
-      const float wyz = q.w * stencil_weight<ASSIGN>(base_offset<ASSIGN>(uy), oy) *
-                        stencil_weight<ASSIGN>(base_offset<ASSIGN>(uz), oz);
-      const int ix = base_index<ASSIGN>(ux, N);
+      // the source row fixes the base cells along y and z; their offsets set the weights
+      const float wyz = q.w * stencil_weight<ASSIGN>(axis_cell<ASSIGN>(q.y, a.bmin[1], a.invH, N).f, oy) *
+                        stencil_weight<ASSIGN>(axis_cell<ASSIGN>(q.z, a.bmin[2], a.invH, N).f, oz);
+      const AxisCell cx = axis_cell<ASSIGN>(q.x, a.bmin[0], a.invH, N);
+      const int ix = cx.i;
       float rx = 0.0f, ry = 0.0f, rz = 1.0f;
       if (a.los == 0) {
         // the sort left out every particle with a zero FP32 line of sight (los_norm2)
@@ -205,7 +204,7 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
         ry = dy * inv;
         rz = dz * inv;
       }
-      rec[j] = make_float4(base_offset<ASSIGN>(ux), wyz, rx, ry);
+      rec[j] = make_float4(cx.f, wyz, rx, ry);
       rzv[j] = rz;
       slot[j] = ((uint32_t)ix << 16) | atomicAdd(&cnt[ix], 1u);
     }
@@ -437,10 +436,10 @@ static hipError_t launch_x1(const Plan& p, char* ws, const XArgs& a, hipStream_t
 hipError_t launch_xpass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   XArgs a;
   for (int i = 0; i < 3; ++i) {
-    a.bmin[i] = (float)p.box_min[i];
+    a.bmin[i] = p.box_min[i];
     a.obs[i] = (float)p.observer[i];
   }
-  a.invH = (float)((double)p.N / p.L);
+  a.invH = (double)p.N / p.L;
   a.los = p.los;
   a.Kx = p.Kx;
   a.z0 = z0;

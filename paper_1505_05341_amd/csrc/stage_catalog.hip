@@ -170,8 +170,7 @@ hipError_t launch_stats(const Plan& p, const pk_catalog& gal, const pk_catalog& 
 // particles are flagged and left out; the host turns a flag into an error.
 // --------------------------------------------------------------------------------
 struct SortGeom {
-  float bmin[3];
-  float invH;
+  double invH;     // N / L
   double bmin_d[3];
   double L;
   float obs[3];   // the observer rounded to FP32, as the assignment takes it
@@ -216,7 +215,7 @@ __global__ __launch_bounds__(256) void plane_hist_kernel(pk_catalog gal, pk_cata
     const float* q = i < gal.n ? gal.xyz + 3 * i : ran.xyz + 3 * (i - gal.n);
     const float x = q[0], y = q[1], z = q[2];
     if (!valid_particle<true>(g, x, y, z, flags)) continue;
-    atomicAdd(&h[base_index<ASSIGN>(grid_coord(z, g.bmin[2], g.invH), g.N)], 1u);
+    atomicAdd(&h[axis_cell<ASSIGN>(z, g.bmin_d[2], g.invH, g.N).i], 1u);
   }
   __syncthreads();
   for (int pl = threadIdx.x; pl < g.N; pl += blockDim.x) ph[(int64_t)pl * gridDim.x + blockIdx.x] = h[pl];
@@ -334,8 +333,8 @@ __global__ __launch_bounds__(kSortThreads) void plane_scatter_kernel(pk_catalog 
       v[j] = raw[j];
       // flags were raised by the histogram pass; here invalid particles are skipped
       if (i < i1 && valid_particle<false>(g, raw[j].x, raw[j].y, raw[j].z, nullptr)) {
-        key[j] = base_index<ASSIGN>(grid_coord(raw[j].z, g.bmin[2], g.invH), g.N);
-        row[j] = base_index<ASSIGN>(grid_coord(raw[j].y, g.bmin[1], g.invH), g.N);
+        key[j] = axis_cell<ASSIGN>(raw[j].z, g.bmin_d[2], g.invH, g.N).i;
+        row[j] = axis_cell<ASSIGN>(raw[j].y, g.bmin_d[1], g.invH, g.N).i;
         if (i >= gal.n) v[j].w = -alpha * raw[j].w;
         rank[j] = atomicAdd(&tcnt[key[j]], 1u);
       }
@@ -560,11 +559,10 @@ __global__ __launch_bounds__(256) void scan_down_kernel(const uint32_t* cnt, int
 static SortGeom sort_geom(const Plan& p) {
   SortGeom g;
   for (int i = 0; i < 3; ++i) {
-    g.bmin[i] = (float)p.box_min[i];
     g.bmin_d[i] = p.box_min[i];
     g.obs[i] = (float)p.observer[i];
   }
-  g.invH = (float)((double)p.N / p.L);
+  g.invH = (double)p.N / p.L;
   g.L = p.L;
   g.N = p.N;
   g.los = p.los;

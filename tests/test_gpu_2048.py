@@ -24,9 +24,9 @@ from paper_1505_05341_amd import catalogs
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 TOL = 1e-5
-# row bound of the full-size tests (FP32 cell coordinates, error ~ |u| 2^-24 per weight)
-# with u up to 2048
-XTOL_2048 = 1.6e-4
+# row bound of the full-size tests (cells from FP64 coordinates, FP32 offsets, weights and
+# sums: a few eps_32 per term relative to the row's sum of |terms|, at any N)
+XTOL_2048 = 1e-5
 
 
 @pytest.fixture(scope="module")

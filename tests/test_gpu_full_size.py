@@ -26,14 +26,13 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 TOL = 1e-5
 # Rows: the weights of galaxies and randoms cancel in a row (the row is a density
 # contrast), so the error is measured against the sum of |terms| (l1) instead of the
-# row's own size. The kernel takes u = (x - box_min) N / L in FP32 with box_min and N / L
-# rounded to FP32, so every particle's offset inside its cell, hence every CIC weight,
-# is off by up to ~|u| 2^-24, and near the top of the box (u ~ 512) that error has the
-# same sign for all particles of a row: up to 512 x 6e-8 = 3e-5 of l1 in the worst case
-# (observed 1e-7 to 1.5e-5), on top of a few eps_32 from the cell sums and the radix
-# stages. A lost or misplaced particle would show as ~1 / 1500 ~ 7e-4 of l1.
-XTOL = 4e-5
-XTOL_1024 = 8e-5  # the same bound with u up to 1024
+# row's own size. The kernel forms u = (x - box_min) N / L in FP64 as the oracle does (the
+# same cells) and rounds only the offset inside the cell to FP32 (error <= 2^-25), so each
+# weight carries a few eps_32 of relative error, and the cell sums and the radix stages a
+# few more: ~1e-6 of l1 at any N. A lost or misplaced particle would show as
+# ~1 / 1500 ~ 7e-4 of l1.
+XTOL = 1e-5
+XTOL_1024 = XTOL
 
 
 @pytest.fixture(scope="module")
