@@ -38,21 +38,27 @@ struct AxisCell {
 
 template <int ASSIGN>
 __device__ __forceinline__ AxisCell axis_cell(float x, double bmin, double invH, int N) {
-  const double u = __dmul_rn(__dsub_rn((double)x, bmin), invH);
-  const double fl = floor(ASSIGN == PK_CIC ? u : __dadd_rn(u, 0.5));
+  // every operation rounded on its own (no fused multiply-add), so that each caller takes
+  // the same cells as the others and as the oracle
+#pragma clang fp contract(off)
+  const double u = ((double)x - bmin) * invH;
+  const double fl = floor(ASSIGN == PK_CIC ? u : u + 0.5);
   AxisCell c;
   c.i = (int)fl & (N - 1);
-  c.f = (float)__dsub_rn(u, fl);
+  c.f = (float)(u - fl);
   return c;
 }
 
-// Weight of the cell at base + o for offset o in [0, 1] (CIC) or [-1, 1] (TSC).
+// Weight of the cell at base + o for offset o in [0, 1] (CIC) or [-1, 1] (TSC). Both TSC
+// forms are evaluated and one is selected: o often differs between the lanes of a wave,
+// and a branch on it would run both sides one after the other.
 template <int ASSIGN>
 __device__ __forceinline__ float stencil_weight(float f, int o) {
   if (ASSIGN == PK_CIC) return o == 0 ? 1.0f - f : f;
-  if (o == 0) return 0.75f - f * f;
-  const float h = o < 0 ? 0.5f - f : 0.5f + f;
-  return 0.5f * h * h;
+  const float h = 0.5f + (o < 0 ? -f : f);
+  const float side = 0.5f * h * h;
+  const float mid = 0.75f - f * f;
+  return o == 0 ? mid : side;
 }
 
 }  // namespace pk

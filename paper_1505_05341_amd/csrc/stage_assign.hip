@@ -106,14 +106,7 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
 // 3/4 - d^2 for o = 0 and (1/2 + o d)^2 / 2 for o = +-1.
 template <int NG, int ASSIGN>
 __device__ __forceinline__ void add_particle(float (&acc)[NG], const float4 p, const float rz, const int o) {
-  float wx;
-  if (ASSIGN == PK_CIC) {
-    wx = o != 0 ? p.x : 1.0f - p.x;
-  } else {
-    const float h = 0.5f + (float)o * p.x;
-    wx = o == 0 ? 0.75f - p.x * p.x : 0.5f * h * h;
-  }
-  const float w = p.y * wx;
+  const float w = p.y * stencil_weight<ASSIGN>(p.x, o);
   float m[NG];
   kept_monomials<NG>(p.z, p.w, rz, m);
 #pragma unroll
@@ -145,6 +138,12 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
     for (int g = 0; g < NG; ++g) acc[c][g] = 0.0f;
+  // index shift from a particle's place in the concatenated source rows to its place in
+  // the sorted array, per source row (modulo 2^32, like every particle index here)
+  __shared__ uint32_t shift[S * S];
+#pragma unroll
+  for (int k = 0; k < S * S; ++k)  // constant indices: beg and pre stay in scalar registers
+    if (tid == k) shift[k] = beg[k] - pre[k];
   for (int i = tid; i < N; i += NT) cnt[i] = 0u;
   __syncthreads();
   const uint32_t total = pre[S * S];
@@ -156,25 +155,24 @@ __device__ __forceinline__ void gather_rows(float* lds, const float4* __restrict
     float4 qv[XPER];
 #pragma unroll
     for (int j = 0; j < XPER; ++j) qv[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // source row of each particle: the number of row starts at or before its place f
+    // (compares against scalars; selecting the row's start and offset alongside took three
+    // selects per row), then its index in the sorted array through the row's shift: all
+    // LDS reads first, then all global loads
     int sv[XPER];
+    uint32_t gi[XPER];
 #pragma unroll
     for (int j = 0; j < XPER; ++j) {
-      const int i = tid + j * NT;
-      sv[j] = 0;
-      if (i < n) {
-        const uint32_t f = c0 + i;
-        uint32_t b0 = beg[0], p0 = 0;
+      const uint32_t f = c0 + tid + j * NT;
+      int k0 = 0;
 #pragma unroll
-        for (int k = 1; k < S * S; ++k) {
-          if (f >= pre[k]) {
-            sv[j] = k;
-            b0 = beg[k];
-            p0 = pre[k];
-          }
-        }
-        qv[j] = sorted[b0 + (f - p0)];
-      }
+      for (int k = 1; k < S * S; ++k) k0 += f >= pre[k] ? 1 : 0;
+      sv[j] = k0;
+      gi[j] = f + shift[k0];
     }
+#pragma unroll
+    for (int j = 0; j < XPER; ++j)
+      if (tid + j * NT < n) qv[j] = sorted[gi[j]];
     // each particle's record stays in registers until its slot in base-cell order is
     // known: its rank inside its cell is the count the atomic returns, its cell's first
     // slot comes from the scan (no unsorted copy, no index permutation)
@@ -297,7 +295,9 @@ __global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
   using F = Fft<N>;
   static_assert(NP * F::T <= XGeom<N, ASSIGN>::NT, "row pairs do not fit the block");
-  extern __shared__ float lds[];
+  // 16-byte aligned: the records are read and written as float4, and the static LDS
+  // (scan sums, row shifts) in front of this area need not be a multiple of 16 bytes
+  extern __shared__ __align__(16) float lds[];
   const int tid = threadIdx.x;
   // first thread index of this wave, a scalar: the output stage forms its kx from it and
   // the hardware lane count instead of holding tid through the gather and the transform
