@@ -204,14 +204,45 @@ struct ZArgs {
   const TileTable* tt;
 };
 
-// Adds NV values of this lane's mode to bins[b][first .. first+NV) with LDS FP64
-// atomics (on gfx950 these run at ~2.4 lane-ops/clk/CU spread and ~0.9 when a wave's
-// lanes share a few bins, far cheaper than cross-lane shuffle reductions).
-template <int NV>
-__device__ __forceinline__ void bin_add(double* bins, int b, bool valid, const double (&v)[NV], int first) {
-  if (!valid) return;
+// Lane i - S of the same 16-lane row (DPP row shift; a lane with no source reads 0).
+template <int S>
+__device__ __forceinline__ int dpp_shr(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x110 + S, 0xf, 0xf, true);
+}
+template <int S>
+__device__ __forceinline__ double dpp_shr(double v) {
+  const int lo = dpp_shr<S>(__double2loint(v)), hi = dpp_shr<S>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+template <int TK, int S, int NV>
+__device__ __forceinline__ void run_step(int c, int key, double (&v)[NV]) {
+  if constexpr (S < TK) {
+    // the shift is taken by every lane (as the left operand of a short-circuit && it would
+    // run only where c >= S and read the others as disabled lanes)
+    const int left = dpp_shr<S>(key);
+    const bool take = (c >= S) & (left == key);
 #pragma unroll
-  for (int j = 0; j < NV; ++j) atomicAdd(&bins[b * kNumSums + first + j], v[j]);
+    for (int j = 0; j < NV; ++j) {
+      const double u = dpp_shr<S>(v[j]);
+      v[j] += take ? u : 0.0;
+    }
+    run_step<TK, 2 * S, NV>(c, key, v);
+  }
+}
+
+// The TK lanes c = 0 .. TK-1 of a column tile hold the same (ky, kz) at kx = kx0 + c, so
+// their bins do not decrease with c and lanes of one bin are adjacent. A segmented
+// inclusive sum over each run of equal keys (DPP row shifts: TK <= 16 divides the row)
+// leaves the run's totals in its last lane, which alone adds them to LDS; this takes the
+// same-address conflicts out of the atomics. Every lane of the wave must execute it
+// (a disabled source lane would be read as 0). Returns whether this lane adds.
+template <int TK, int NV>
+__device__ __forceinline__ bool run_total(int c, int key, double (&v)[NV]) {
+  static_assert(TK <= 16 && (TK & (TK - 1)) == 0, "tiles of up to 16 columns");
+  run_step<TK, 1, NV>(c, key, v);
+  const int next = __builtin_amdgcn_update_dpp(0, key, 0x101, 0xf, 0xf, true);  // lane i + 1 (row_shl:1)
+  return c == TK - 1 || next != key;
 }
 
 __device__ __forceinline__ int isqrt_i(int n) {
@@ -397,9 +428,14 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
           w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
         }
         // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise, 6 Q6
-        bin_add<4>(bins, b, valid, w4, 0);
-        double w1[1] = {mu * S * (double)noise_f};
-        bin_add<1>(bins, b, valid, w1, 5);
+        double w5[5] = {w4[0], w4[1], w4[2], w4[3], mu * S * (double)noise_f};
+        const int key = valid ? b : -1 - c;  // invalid lanes: a key no neighbour holds
+        const bool last = run_total<TK>(c, key, w5);
+        if (valid && last) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) atomicAdd(&bins[b * kNumSums + j], w5[j]);
+          atomicAdd(&bins[b * kNumSums + 5], w5[4]);
+        }
       }
     }
     if (ELL >= 4) {
@@ -419,7 +455,8 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const float2 z0 = a0[e];
         const float2 A4 = acc[e];
         double w[1] = {mu * (double)((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw)};
-        bin_add<1>(bins, b, valid, w, 4);
+        const bool last = run_total<TK>(c, valid ? b : -1 - c, w);
+        if (valid && last) atomicAdd(&bins[b * kNumSums + 4], w[0]);
       }
     }
     if (ELL >= 6) {
@@ -440,7 +477,8 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const float2 z0 = a0[e];
         const float2 A6 = acc[e];
         double w[1] = {mu * (double)((z0.x * A6.x + z0.y * A6.y) * inv_t6 * iw)};
-        bin_add<1>(bins, b, valid, w, 6);
+        const bool last = run_total<TK>(c, valid ? b : -1 - c, w);
+        if (valid && last) atomicAdd(&bins[b * kNumSums + 6], w[0]);
       }
     }
     cur = nxt;
