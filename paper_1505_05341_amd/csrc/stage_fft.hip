@@ -53,6 +53,13 @@ struct ColSlot {
 template <int N>
 constexpr int tile_cols() { return N >= 2048 ? 4 : (N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16)); }
 
+// kx columns per y-pass block: half a tile of H at N = 512 and 1024, so that two blocks
+// (8 and 16 values per thread respectively need 96 and ~230 registers) share a CU and
+// one block's barriers overlap the other's work; two neighbouring blocks (on one XCD)
+// fill the two halves of each H tile row. A whole tile elsewhere.
+template <int N>
+constexpr int ytile_cols() { return (N == 512 || N == 1024) ? tile_cols<N>() / 2 : tile_cols<N>(); }
+
 // Linear block id -> logical id such that blocks with consecutive logical ids run on one
 // XCD (workgroups go to the 8 XCDs round-robin): tiles narrower than a 128-byte line
 // share lines with their neighbours, which then meet in that XCD's L2. Needs a multiple
@@ -94,9 +101,10 @@ __device__ __forceinline__ void load_member(const float2* __restrict__ X, const 
   }
 }
 
-template <int N, int TK, int EC>
+template <int N, int TK, int EC, int TKH>
 __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
                                                                   const float2* __restrict__ tw, const YArgs a) {
+  static_assert(TKH % TK == 0, "a y tile is a part of an H tile");
   using F = Fft<N, EC>;
   extern __shared__ float2 T[];
   // The flattened member table and the twiddles, in LDS: loads of global memory retire
@@ -118,8 +126,10 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
   }
   for (int i = tid0; i < ngroups; i += blockDim.x) s_end[i] = gt.mend[i];
   for (int i = tid0; i < N; i += blockDim.x) twl[i] = tw[i];
-  const int M = a.tt->M[kt];
-  const int64_t regoff = a.tt->regoff[kt];
+  // the H tile (TKH columns) this block's TK columns belong to, and their offset in it
+  const int kth = kt * TK / TKH, ch = kt * TK - kth * TKH;
+  const int M = a.tt->M[kth];
+  const int64_t regoff = a.tt->regoff[kth];
   const int nslot = 2 * M + 1;
   // the EC = 16 schedule keeps the ty of its values in registers
   float tyv[F::E];
@@ -155,16 +165,16 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float
       }
     }
     const int c = tid0 % TK, t = tid0 / TK;
-    float2* __restrict__ dst = H + (size_t)g * a.h_group_stride + regoff + (size_t)z * nslot * TK + c;
+    float2* __restrict__ dst = H + (size_t)g * a.h_group_stride + regoff + (size_t)z * nslot * TKH + ch + c;
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
       const int ky = signed_freq<N>(F::out_index(t, e));
-      if (ky >= -M && ky <= M) dst[(size_t)(ky + M) * TK] = acc[e];
+      if (ky >= -M && ky <= M) dst[(size_t)(ky + M) * TKH] = acc[e];
     }
   }
 }
 
-template <int N, int TK>
+template <int N, int TK, int TKH>
 static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   YArgs a;
   a.Kx = p.Kx;
@@ -175,15 +185,16 @@ static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0, int 
   a.gt = at<const GroupTable>(ws, p.off_tables);
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
   const size_t shmem = (size_t)(TK + 1) * N * sizeof(float2);  // column tile + twiddles
+  const int ntiles = p.nkt * (TKH / TK);                      // y tiles: Kx / TK
   if (N >= 2048 || p.col_e[0] == 8) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8, TKH>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 8>), dim3(p.nkt, p.xs), dim3(TK * Fft<N, 8>::T), shmem, s,
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 8, TKH>), dim3(ntiles, p.xs), dim3(TK * Fft<N, 8>::T), shmem, s,
                        at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
   } else if constexpr (N < 2048) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 16>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 16, TKH>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 16>), dim3(p.nkt, p.xs), dim3(TK * Fft<N, 16>::T), shmem, s,
+    hipLaunchKernelGGL((ypass_kernel<N, TK, 16, TKH>), dim3(ntiles, p.xs), dim3(TK * Fft<N, 16>::T), shmem, s,
                        at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
   }
   return hipGetLastError();
@@ -537,15 +548,15 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
 
 hipError_t launch_ypass(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
   switch (p.N) {
-    case 8: return launch_y2<8, tile_cols<8>()>(p, ws, s, z0, pbase);
-    case 16: return launch_y2<16, tile_cols<16>()>(p, ws, s, z0, pbase);
-    case 32: return launch_y2<32, tile_cols<32>()>(p, ws, s, z0, pbase);
-    case 64: return launch_y2<64, tile_cols<64>()>(p, ws, s, z0, pbase);
-    case 128: return launch_y2<128, tile_cols<128>()>(p, ws, s, z0, pbase);
-    case 256: return launch_y2<256, tile_cols<256>()>(p, ws, s, z0, pbase);
-    case 512: return launch_y2<512, tile_cols<512>()>(p, ws, s, z0, pbase);
-    case 1024: return launch_y2<1024, tile_cols<1024>()>(p, ws, s, z0, pbase);
-    case 2048: return launch_y2<2048, tile_cols<2048>()>(p, ws, s, z0, pbase);
+    case 8: return launch_y2<8, ytile_cols<8>(), tile_cols<8>()>(p, ws, s, z0, pbase);
+    case 16: return launch_y2<16, ytile_cols<16>(), tile_cols<16>()>(p, ws, s, z0, pbase);
+    case 32: return launch_y2<32, ytile_cols<32>(), tile_cols<32>()>(p, ws, s, z0, pbase);
+    case 64: return launch_y2<64, ytile_cols<64>(), tile_cols<64>()>(p, ws, s, z0, pbase);
+    case 128: return launch_y2<128, ytile_cols<128>(), tile_cols<128>()>(p, ws, s, z0, pbase);
+    case 256: return launch_y2<256, ytile_cols<256>(), tile_cols<256>()>(p, ws, s, z0, pbase);
+    case 512: return launch_y2<512, ytile_cols<512>(), tile_cols<512>()>(p, ws, s, z0, pbase);
+    case 1024: return launch_y2<1024, ytile_cols<1024>(), tile_cols<1024>()>(p, ws, s, z0, pbase);
+    case 2048: return launch_y2<2048, ytile_cols<2048>(), tile_cols<2048>()>(p, ws, s, z0, pbase);
     default: return hipErrorInvalidValue;
   }
 }
