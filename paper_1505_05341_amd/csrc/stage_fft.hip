@@ -226,35 +226,48 @@ __device__ __forceinline__ double dpp_shr(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int TK, int S, int NV>
-__device__ __forceinline__ void run_step(int c, int key, double (&v)[NV]) {
-  if constexpr (S < TK) {
-    // the shift is taken by every lane (as the left operand of a short-circuit && it would
-    // run only where c >= S and read the others as disabled lanes)
-    const int left = dpp_shr<S>(key);
-    const bool take = (c >= S) & (left == key);
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      const double u = dpp_shr<S>(v[j]);
-      v[j] += take ? u : 0.0;
-    }
-    run_step<TK, 2 * S, NV>(c, key, v);
-  }
-}
-
 // The TK lanes c = 0 .. TK-1 of a column tile hold the same (ky, kz) at kx = kx0 + c, so
 // their bins do not decrease with c and lanes of one bin are adjacent. A segmented
 // inclusive sum over each run of equal keys (DPP row shifts: TK <= 16 divides the row)
 // leaves the run's totals in its last lane, which alone adds them to LDS; this takes the
-// same-address conflicts out of the atomics. Every lane of the wave must execute it
-// (a disabled source lane would be read as 0). Returns whether this lane adds.
-template <int TK, int NV>
-__device__ __forceinline__ bool run_total(int c, int key, double (&v)[NV]) {
+// same-address conflicts out of the atomics. Every lane of the wave must execute the
+// shifts (a disabled source lane would be read as 0).
+template <int TK>
+struct Runs {
   static_assert(TK <= 16 && (TK & (TK - 1)) == 0, "tiles of up to 16 columns");
-  run_step<TK, 1, NV>(c, key, v);
-  const int next = __builtin_amdgcn_update_dpp(0, key, 0x101, 0xf, 0xf, true);  // lane i + 1 (row_shl:1)
-  return c == TK - 1 || next != key;
-}
+  bool take[4];  // step s (shift 2^s): the lane 2^s below is in this lane's run
+  bool last;     // this lane ends its run: it alone adds the run's totals
+
+  __device__ __forceinline__ Runs(int c, int key) {
+    // every shift is taken by every lane (as the right operand of a short-circuit && a
+    // shift would run only where the left one holds, and read the other lanes as disabled)
+    take[0] = (c >= 1) & (dpp_shr<1>(key) == key);
+    take[1] = (c >= 2) & (dpp_shr<2>(key) == key);
+    take[2] = (c >= 4) & (dpp_shr<4>(key) == key);
+    take[3] = (c >= 8) & (dpp_shr<8>(key) == key);
+    const int next = __builtin_amdgcn_update_dpp(0, key, 0x101, 0xf, 0xf, true);  // lane i + 1 (row_shl:1)
+    last = (c == TK - 1) | (next != key);
+  }
+
+  // Inclusive segmented sums of v over the runs (a few values at a time keeps the shifted
+  // copies in few registers).
+  template <int NV>
+  __device__ __forceinline__ void sum(double (&v)[NV]) const {
+    step<1>(v);
+    if constexpr (TK > 2) step<2>(v);
+    if constexpr (TK > 4) step<4>(v);
+    if constexpr (TK > 8) step<8>(v);
+  }
+  template <int S, int NV>
+  __device__ __forceinline__ void step(double (&v)[NV]) const {
+    constexpr int k = S == 1 ? 0 : (S == 2 ? 1 : (S == 4 ? 2 : 3));
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const double u = dpp_shr<S>(v[j]);
+      v[j] += take[k] ? u : 0.0;
+    }
+  }
+};
 
 __device__ __forceinline__ int isqrt_i(int n) {
   int s = (int)sqrtf((float)n);
@@ -439,13 +452,20 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
           w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
         }
         // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise, 6 Q6
-        double w5[5] = {w4[0], w4[1], w4[2], w4[3], mu * S * (double)noise_f};
-        const int key = valid ? b : -1 - c;  // invalid lanes: a key no neighbour holds
-        const bool last = run_total<TK>(c, key, w5);
-        if (valid && last) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) atomicAdd(&bins[b * kNumSums + j], w5[j]);
-          atomicAdd(&bins[b * kNumSums + 5], w5[4]);
+        const Runs<TK> runs(c, valid ? b : -1 - c);  // invalid lanes: a key no neighbour holds
+        const bool add = valid && runs.last;
+        double wa[3] = {w4[0], w4[1], mu * S * (double)noise_f};
+        runs.sum(wa);
+        if (add) {
+          atomicAdd(&bins[b * kNumSums + 0], wa[0]);
+          atomicAdd(&bins[b * kNumSums + 1], wa[1]);
+          atomicAdd(&bins[b * kNumSums + 5], wa[2]);
+        }
+        double wb[2] = {w4[2], w4[3]};
+        runs.sum(wb);
+        if (add) {
+          atomicAdd(&bins[b * kNumSums + 2], wb[0]);
+          atomicAdd(&bins[b * kNumSums + 3], wb[1]);
         }
       }
     }
@@ -466,8 +486,9 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const float2 z0 = a0[e];
         const float2 A4 = acc[e];
         double w[1] = {mu * (double)((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw)};
-        const bool last = run_total<TK>(c, valid ? b : -1 - c, w);
-        if (valid && last) atomicAdd(&bins[b * kNumSums + 4], w[0]);
+        const Runs<TK> runs(c, valid ? b : -1 - c);
+        runs.sum(w);
+        if (valid && runs.last) atomicAdd(&bins[b * kNumSums + 4], w[0]);
       }
     }
     if (ELL >= 6) {
@@ -488,8 +509,9 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
         const float2 z0 = a0[e];
         const float2 A6 = acc[e];
         double w[1] = {mu * (double)((z0.x * A6.x + z0.y * A6.y) * inv_t6 * iw)};
-        const bool last = run_total<TK>(c, valid ? b : -1 - c, w);
-        if (valid && last) atomicAdd(&bins[b * kNumSums + 6], w[0]);
+        const Runs<TK> runs(c, valid ? b : -1 - c);
+        runs.sum(w);
+        if (valid && runs.last) atomicAdd(&bins[b * kNumSums + 6], w[0]);
       }
     }
     cur = nxt;
