@@ -40,6 +40,10 @@ def test_traffic_is_reported_only_for_the_workload_it_was_measured_on():
     keys = list(bench.TRAFFIC)
     assert keys and all(isinstance(k, tuple) and len(k) == 2 for k in keys)
     for workload, kernel in keys:
+        t = bench.TRAFFIC[(workload, kernel)]
+        got = bench.measured_traffic(workload, kernel)
+        if got is not None:  # sources unchanged since the counters were taken
+            assert got == 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
         for other in ("desi_1024", "survey", "tiny_32", "clustered_512"):
-            if other != workload:
+            if (other, kernel) not in bench.TRAFFIC:
                 assert bench.measured_traffic(other, kernel) is None
