@@ -60,6 +60,12 @@ constexpr int tile_cols() { return N >= 2048 ? 4 : (N >= 1024 ? 8 : (N / 2 < 16 
 template <int N>
 constexpr int ytile_cols() { return (N == 512 || N == 1024) ? tile_cols<N>() / 2 : tile_cols<N>(); }
 
+// kx columns per z-pass block: half an H tile (8 columns, 512 threads) at N = 512, so that
+// two blocks of ~128 registers share a CU instead of one (z pass 1.29 -> 1.16 ms at 512^3);
+// at 1024 half tiles (4 columns) were slower (11.7 -> 12.1 ms): whole tiles there.
+template <int N>
+constexpr int ztile_cols() { return N == 512 ? tile_cols<N>() / 2 : tile_cols<N>(); }
+
 // Linear block id -> logical id such that blocks with consecutive logical ids run on one
 // XCD (workgroups go to the 8 XCDs round-robin): tiles narrower than a 128-byte line
 // share lines with their neighbours, which then meet in that XCD's L2. Needs a multiple
@@ -276,26 +282,30 @@ __device__ __forceinline__ int isqrt_i(int n) {
   return s;
 }
 
-// Column (kx tile, ky) of the z pass: its H address (group 0), tile and row stride.
+// Column (kx tile, ky) of the z pass: its H address (group 0), tile, part of the tile and
+// row stride. A block takes TK columns: a whole H tile (HP = 1) or one of its HP parts;
+// the HP parts of one (tile, ky) are consecutive items, which go to one XCD.
 struct ZItem {
   const float2* base;
-  int kt, M, s, zstride;
+  int kt, part, M, s, zstride;
 };
 
-template <int TK>
+template <int TK, int HP>
 __device__ __forceinline__ ZItem z_item(int64_t item, const float2* __restrict__ H, const int64_t* item0,
                                         const int64_t* regoff, const int* Mt, int nkt, int c) {
-  int kt = 0, hi = nkt;  // the tile: the last kt with item0[kt] <= item
+  const int64_t key = item / HP;  // the (tile, ky) column
+  int kt = 0, hi = nkt;           // the tile: the last kt with item0[kt] <= key
   while (hi - kt > 1) {
     const int mid = (kt + hi) >> 1;
-    if (item0[mid] <= item) kt = mid; else hi = mid;
+    if (item0[mid] <= key) kt = mid; else hi = mid;
   }
   ZItem z;
   z.kt = kt;
+  z.part = (int)(item - key * HP);
   z.M = Mt[kt];
-  z.s = (int)(item - item0[kt]);
-  z.zstride = (2 * z.M + 1) * TK;
-  z.base = H + regoff[kt] + (size_t)z.s * TK + c;
+  z.s = (int)(key - item0[kt]);
+  z.zstride = (2 * z.M + 1) * TK * HP;
+  z.base = H + regoff[kt] + (size_t)z.s * TK * HP + z.part * TK + c;
   return z;
 }
 
@@ -363,8 +373,8 @@ __host__ __device__ constexpr size_t zpass_lds_bytes(int N, int TK, int nbins, i
          (size_t)2 * N * 4 + (size_t)nkt * 4;
 }
 
-template <int N, int TK, int ELL, int EC>
-__global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float2* __restrict__ H,
+template <int N, int TK, int ELL, int EC, int HP>
+__global__ __launch_bounds__((TK * Fft<N, EC>::T)) __attribute__((amdgpu_waves_per_eu(EC == 8 ? 4 : 1, 8))) void zpass_kernel(const float2* __restrict__ H,
                                                                   const float2* __restrict__ tw,
                                                                   const float* __restrict__ invw2,
                                                                   const float* __restrict__ alias,
@@ -402,7 +412,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
   // consecutive items (neighbouring ky columns of one tile, which share lines when the
   // tile is narrower than 128 bytes) go to blocks of one XCD
   int64_t item = xcd_group(blockIdx.x, gridDim.x);
-  ZItem cur = z_item<TK>(item < a.n_items ? item : 0, H, item0, regoff, Mt, a.nkt, c);
+  ZItem cur = z_item<TK, HP>(item < a.n_items ? item : 0, H, item0, regoff, Mt, a.nkt, c);
   float2 nd[F::E];  // defined on every path (an undefined value can pin its register)
 #pragma unroll
   for (int e = 0; e < F::E; ++e) nd[e] = make_float2(0.0f, 0.0f);
@@ -410,10 +420,10 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
   for (; item < a.n_items; item += gridDim.x) {
     const int64_t nitem = item + gridDim.x;
     const bool more = nitem < a.n_items;
-    const ZItem nxt = more ? z_item<TK>(nitem, H, item0, regoff, Mt, a.nkt, c) : cur;
+    const ZItem nxt = more ? z_item<TK, HP>(nitem, H, item0, regoff, Mt, a.nkt, c) : cur;
     const int M = cur.M;
     const int ky = cur.s - M;
-    const int kx = cur.kt * TK + c;
+    const int kx = cur.kt * (TK * HP) + cur.part * TK + c;
     const float tx = (float)kx * twoN, ty = (float)ky * twoN;
     const float wxy = ivw[kx] * ivw[ky & (N - 1)];
     const float cxy = alw[kx] * alw[ky & (N - 1)];
@@ -521,12 +531,12 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void zpass_kernel(const float
   for (int i = tid; i < a.nbins * kNumSums; i += blockDim.x) out[i] = bins[i];
 }
 
-template <int N, int TK, int ELL, int EC>
+template <int N, int TK, int ELL, int EC, int HP>
 static hipError_t launch_z4(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
   const size_t shmem = zpass_lds_bytes(N, TK, p.nbins, p.nkt);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL, EC>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&zpass_kernel<N, TK, ELL, EC, HP>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((zpass_kernel<N, TK, ELL, EC>), dim3(p.z_blocks), dim3(TK * Fft<N, EC>::T), shmem, s,
+  hipLaunchKernelGGL((zpass_kernel<N, TK, ELL, EC, HP>), dim3(p.z_blocks), dim3(TK * Fft<N, EC>::T), shmem, s,
                      at<const float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), at<const float>(ws, p.off_invw2),
                      at<const float>(ws, p.off_alias), at<const double>(ws, p.off_scalars),
                      at<double>(ws, p.off_zpart), a);
@@ -535,17 +545,20 @@ static hipError_t launch_z4(const Plan& p, char* ws, const ZArgs& a, hipStream_t
 
 // At N = 2048 only the 8-value schedule is built: with 16 values per thread the column
 // transforms need more than 256 registers.
-template <int N, int TK, int ELL>
+template <int N, int TK, int ELL, int HP>
 static hipError_t launch_z3(const Plan& p, char* ws, const ZArgs& a, hipStream_t s) {
   if constexpr (N >= 2048) {
-    return launch_z4<N, TK, ELL, 8>(p, ws, a, s);
+    return launch_z4<N, TK, ELL, 8, HP>(p, ws, a, s);
   } else {
-    return p.col_e[1] == 8 ? launch_z4<N, TK, ELL, 8>(p, ws, a, s) : launch_z4<N, TK, ELL, 16>(p, ws, a, s);
+    return p.col_e[1] == 8 ? launch_z4<N, TK, ELL, 8, HP>(p, ws, a, s) : launch_z4<N, TK, ELL, 16, HP>(p, ws, a, s);
   }
 }
 
-template <int N, int TK>
+// TKH: columns of an H tile; the z blocks take ztile_cols<N>() of them.
+template <int N, int TKH>
 static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
+  constexpr int TK = ztile_cols<N>(), HP = TKH / TK;
+  static_assert(TKH % TK == 0, "a z block takes a part of an H tile");
   ZArgs a;
   a.Kx = p.Kx;
   a.K2 = p.K * p.K;
@@ -554,15 +567,15 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
   a.compensate = p.compensate;
   a.nkt = p.nkt;
   a.h_group_stride = (int64_t)p.H_group_stride;
-  a.n_items = p.z_items;
+  a.n_items = p.z_items * HP;
   a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
   switch (p.ell_max) {
-    case 0: return launch_z3<N, TK, 0>(p, ws, a, s);
-    case 2: return launch_z3<N, TK, 2>(p, ws, a, s);
+    case 0: return launch_z3<N, TK, 0, HP>(p, ws, a, s);
+    case 2: return launch_z3<N, TK, 2, HP>(p, ws, a, s);
     case 6:
-      if constexpr (N <= 1024) return launch_z3<N, TK, 6>(p, ws, a, s);
+      if constexpr (N <= 1024) return launch_z3<N, TK, 6, HP>(p, ws, a, s);
       else return hipErrorInvalidValue;
-    default: return launch_z3<N, TK, 4>(p, ws, a, s);
+    default: return launch_z3<N, TK, 4, HP>(p, ws, a, s);
   }
 }
 
