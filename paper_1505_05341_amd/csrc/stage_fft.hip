@@ -1,17 +1,20 @@
 // Transforms along y and z, the k-hat contraction and the shell binning
 // (Sec. 3, Eqs. 6-13).
 //
-// y pass: one block owns a tile of TK kx columns at one z. For every monomial grid it
-//   loads the N x TK tile (TK complex values per row, coalesced), transforms along y
-//   and multiplies by coef_m tx^a ty^b; the grids of one group (degree n, power c of
-//   z) are summed in registers, so each group leaves a single grid H_{n,c}. Only the
-//   rows with kx0^2 + ky^2 < K^2 are stored (kx0 = the tile's smallest kx).
-// z pass: a persistent block walks (kx tile, ky) columns. It transforms H_{0,0}
-//   along z to A_0, accumulates A_n = |t|^-n sum_c tz^c FFT_z[H_{n,c}] for n = 2, 4
-//   (and 6) (t = 2n/N), and adds per mode
-//   mu Re[A_0 A_l^*] / W^2, the noise and the mode count to FP64 bin sums in LDS
-//   (mu = 1 on the kx = 0 plane, 2 elsewhere: the other half of the lattice holds the
-//   complex conjugates). Each block writes its bin sums once.
+// H is stored in tiles of TKH kx columns (tile_cols): for each group, tile and z, the
+// rows |ky| <= M(tile) of TKH complex values.
+// y pass: one block owns TK kx columns (a whole H tile, or half of one at N = 512 and
+//   1024) at one z. For every monomial grid it loads the N x TK tile (TK complex values
+//   per row, coalesced), transforms along y and multiplies by coef_m tx^a ty^b; the
+//   grids of one group (degree n, power c of z) are summed in registers, so each group
+//   leaves a single grid H_{n,c}. Only the rows with kx0^2 + ky^2 < K^2 are stored
+//   (kx0 = the H tile's smallest kx).
+// z pass: a persistent block walks (kx tile, ky) columns (a whole H tile, or half of
+//   one at N = 512). It transforms H_{0,0} along z to A_0, accumulates
+//   A_n = |t|^-n sum_c tz^c FFT_z[H_{n,c}] for n = 2, 4 (and 6) (t = 2n/N), and adds
+//   per mode mu Re[A_0 A_l^*] / W^2, the noise and the mode count to FP64 bin sums in
+//   LDS (mu = 1 on the kx = 0 plane, 2 elsewhere: the other half of the lattice holds
+//   the complex conjugates). Each block writes its bin sums once.
 //
 // By linearity, A_n = |t|^-n sum_{a+b+c=n} coef tx^a ty^b tz^c FFT_xyz[F rhat^(a,b,c)]
 // equals the paper's Eqs. (10) and (12); regrouping by the power of z only moves the
