@@ -72,36 +72,49 @@ hipError_t launch_init(const Plan& p, char* ws, hipStream_t s) {
 // --------------------------------------------------------------------------------
 __device__ __forceinline__ bool finite_f(float v) { return isfinite(v); }
 
+// Adds one particle's w, w^2 and (with_nb) w^2 nbar to s[0], s[1], s[2].
+__device__ __forceinline__ void stats_add(float w, float nb, bool with_nb, double (&s)[3], bool& bad) {
+  bad |= !finite_f(w);
+  const double wd = w;
+  s[0] += wd;
+  s[1] += wd * wd;
+  if (with_nb) {
+    bad |= !finite_f(nb);
+    s[2] += wd * wd * (double)nb;
+  }
+}
+
+// Sums over one catalogue, grid-stride: 16-byte loads of four weights (and densities)
+// where the arrays are 16-byte aligned, single elements for the rest.
+__device__ __forceinline__ void stats_range(const float* w, const float* nb, int64_t n, bool with_nb, int64_t t0,
+                                            int64_t stride, double (&s)[3], bool& bad) {
+  const uintptr_t al = reinterpret_cast<uintptr_t>(w) | (with_nb ? reinterpret_cast<uintptr_t>(nb) : 0);
+  int64_t done = 0;
+  if ((al & 15) == 0) {
+    const int64_t n4 = n / 4;
+    for (int64_t i = t0; i < n4; i += stride) {
+      const float4 wv = reinterpret_cast<const float4*>(w)[i];
+      const float4 nv = with_nb ? reinterpret_cast<const float4*>(nb)[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      stats_add(wv.x, nv.x, with_nb, s, bad);
+      stats_add(wv.y, nv.y, with_nb, s, bad);
+      stats_add(wv.z, nv.z, with_nb, s, bad);
+      stats_add(wv.w, nv.w, with_nb, s, bad);
+    }
+    done = 4 * n4;
+  }
+  for (int64_t i = done + t0; i < n; i += stride) stats_add(w[i], with_nb ? nb[i] : 0.0f, with_nb, s, bad);
+}
+
 __global__ __launch_bounds__(256) void stats_kernel(pk_catalog gal, pk_catalog ran, int norm_from,
                                                     double* partials, int* flags) {
-  double acc[6] = {0, 0, 0, 0, 0, 0};
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = t0; i < gal.n; i += stride) {
-    const float w = gal.w[i];
-    bad |= !finite_f(w);
-    const double wd = w;
-    acc[0] += wd;
-    acc[2] += wd * wd;
-    if (norm_from == 1) {
-      const float nb = gal.nbar[i];
-      bad |= !finite_f(nb);
-      acc[4] += wd * wd * (double)nb;
-    }
-  }
-  for (int64_t i = t0; i < ran.n; i += stride) {
-    const float w = ran.w[i];
-    bad |= !finite_f(w);
-    const double wd = w;
-    acc[1] += wd;
-    acc[3] += wd * wd;
-    if (norm_from == 0) {
-      const float nb = ran.nbar[i];
-      bad |= !finite_f(nb);
-      acc[5] += wd * wd * (double)nb;
-    }
-  }
+  double sg[3] = {0, 0, 0}, sr[3] = {0, 0, 0};
+  stats_range(gal.w, gal.nbar, gal.n, norm_from == 1, t0, stride, sg, bad);
+  stats_range(ran.w, ran.nbar, ran.n, norm_from == 0, t0, stride, sr, bad);
+  // slots: 0 sum w_g, 1 sum w_r, 2 sum w_g^2, 3 sum w_r^2, 4 sum w_g^2 nbar_g, 5 sum w_r^2 nbar_r
+  double acc[6] = {sg[0], sr[0], sg[1], sr[1], sg[2], sr[2]};
   if (bad) atomicOr(flags, (int)kFlagNonFiniteWeight);
   __shared__ double red[6][256];
 #pragma unroll
@@ -389,7 +402,24 @@ __global__ __launch_bounds__(kSortThreads) void row_hist_kernel(const uint16_t* 
   plane_part(phoff, B, pl, q, lo, hi);
   for (int i = tid; i < N; i += kSortThreads) hc[i] = 0u;
   __syncthreads();
-  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&hc[rowkey[i]], 1u);
+  // eight keys per 16-byte load over the aligned middle of the part, single keys at its ends
+  // (rowkey starts on a 256-byte boundary of the workspace)
+  const uint32_t a0 = (lo + 7u) & ~7u, a1 = hi & ~7u;
+  if (a0 < a1) {
+    for (uint32_t j = a0 / 8 + tid; j < a1 / 8; j += kSortThreads) {
+      const uint4 v = reinterpret_cast<const uint4*>(rowkey)[j];
+      const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        atomicAdd(&hc[u[k] & 0xffffu], 1u);
+        atomicAdd(&hc[u[k] >> 16], 1u);
+      }
+    }
+    if ((uint32_t)tid < a0 - lo) atomicAdd(&hc[rowkey[lo + tid]], 1u);
+    if ((uint32_t)tid < hi - a1) atomicAdd(&hc[rowkey[a1 + tid]], 1u);
+  } else {
+    for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&hc[rowkey[i]], 1u);
+  }
   __syncthreads();
   for (int y = tid; y < N; y += kSortThreads) rh[((int64_t)pl * N + y) * kRowParts + q] = hc[y];
 }
