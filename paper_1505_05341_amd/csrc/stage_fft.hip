@@ -431,7 +431,8 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) __attribute__((amdgpu_waves_p
     const float wxy = ivw[kx] * ivw[ky & (N - 1)];
     const float cxy = alw[kx] * alw[ky & (N - 1)];
     const int n2xy = kx * kx + ky * ky;
-    const double mu = kx == 0 ? 1.0 : 2.0;
+    // 1 or 2: its products with FP32 values are exact in FP32 (kept so: one register)
+    const float mu = kx == 0 ? 1.0f : 2.0f;
 
     float2 a0[F::E];
     z_step<N, TK, EC, NG>(0, nd, a0, cur, nxt, more, a.h_group_stride, c, t, twl, T);
@@ -454,20 +455,20 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) __attribute__((amdgpu_waves_p
         const float2 z0 = a0[e];
         const float q0 = (z0.x * z0.x + z0.y * z0.y) * iw;
         double w4[4];
-        w4[0] = mu;
-        w4[1] = mu * (double)sqrtf((float)n2);
-        w4[2] = mu * (double)q0;
+        w4[0] = (double)mu;
+        w4[1] = (double)(mu * sqrtf((float)n2));
+        w4[2] = (double)(mu * q0);
         w4[3] = 0.0;
         if (ELL >= 2) {
           const float tz = (float)kz * twoN;
           const float inv_t2 = 1.0f / (tx * tx + ty * ty + tz * tz);
           const float2 A2 = acc[e];
-          w4[3] = mu * (double)((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw);
+          w4[3] = (double)(mu * ((z0.x * A2.x + z0.y * A2.y) * inv_t2 * iw));
         }
         // slots: 0 count, 1 |n|, 2 Q0, 3 Q2, 4 Q4, 5 noise, 6 Q6
         const Runs<TK> runs(c, valid ? b : -1 - c);  // invalid lanes: a key no neighbour holds
         const bool add = valid && runs.last;
-        double wa[3] = {w4[0], w4[1], mu * S * (double)noise_f};
+        double wa[3] = {w4[0], w4[1], S * (double)(mu * noise_f)};
         runs.sum(wa);
         if (add) {
           atomicAdd(&bins[b * kNumSums + 0], wa[0]);
@@ -498,7 +499,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) __attribute__((amdgpu_waves_p
         const float inv_t4 = 1.0f / (t2 * t2);
         const float2 z0 = a0[e];
         const float2 A4 = acc[e];
-        double w[1] = {mu * (double)((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw)};
+        double w[1] = {(double)(mu * ((z0.x * A4.x + z0.y * A4.y) * inv_t4 * iw))};
         const Runs<TK> runs(c, valid ? b : -1 - c);
         runs.sum(w);
         if (valid && runs.last) atomicAdd(&bins[b * kNumSums + 4], w[0]);
@@ -521,7 +522,7 @@ __global__ __launch_bounds__((TK * Fft<N, EC>::T)) __attribute__((amdgpu_waves_p
         const float inv_t6 = 1.0f / (t2 * t2 * t2);
         const float2 z0 = a0[e];
         const float2 A6 = acc[e];
-        double w[1] = {mu * (double)((z0.x * A6.x + z0.y * A6.y) * inv_t6 * iw)};
+        double w[1] = {(double)(mu * ((z0.x * A6.x + z0.y * A6.y) * inv_t6 * iw))};
         const Runs<TK> runs(c, valid ? b : -1 - c);
         runs.sum(w);
         if (valid && runs.last) atomicAdd(&bins[b * kNumSums + 6], w[0]);
