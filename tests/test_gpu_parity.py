@@ -203,8 +203,11 @@ def test_repeat_runs_agree(pk):
         raw = np.abs(a["P0"]) + a["noise"]
         ok = a["nmodes"] > 0
         # the assignment sums each cell in FP32 in an order set by atomics: runs agree to
-        # the FP32 rounding of the cells, amplified by at most the P4 cancellation (~10x)
-        assert np.max(np.abs(a["P%d" % ell][ok] - b["P%d" % ell][ok]) / raw[ok]) < 1e-5
+        # the FP32 rounding of the cells (a few 1e-8 of the raw power per cell), amplified
+        # by the P4 cancellation; measured at most 5e-7 over repeated runs on MI355X
+        d = np.max(np.abs(a["P%d" % ell][ok] - b["P%d" % ell][ok]) / raw[ok])
+        print("repeat runs: ell", ell, "max difference %.2e of the raw shell power" % d, flush=True)
+        assert d < 2e-6
 
 
 # ------------------------------------------------------------------------- error paths
@@ -335,7 +338,12 @@ def test_batch_matches_single_calls_and_oracle(pk):
         raw = np.abs(single["P0"]) + single["noise"]
         ok = single["nmodes"] > 0
         for ell in (0, 2, 4):
-            assert np.max(np.abs(res[i]["P%d" % ell][ok] - single["P%d" % ell][ok]) / raw[ok]) < 1e-5
+            # the same kernels; only the FP32 cell-sum order differs (see the repeat-run
+            # test); these mocks have 1,500-5,000 galaxies, so P4 cancels more: measured
+            # at most 8.5e-7 on MI355X
+            d = np.max(np.abs(res[i]["P%d" % ell][ok] - single["P%d" % ell][ok]) / raw[ok])
+            print("batch vs single: mock", i, "ell", ell, "max difference %.2e" % d, flush=True)
+            assert d < 4e-6
         if i in (0, 5):
             ref = est.pk_multipoles(gal.pos, gal.w, ran.pos, ran.w, est.Config(**cfg), gal.nbar, ran.nbar)
             compare(res[i], ref, cfg)
