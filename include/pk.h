@@ -333,6 +333,10 @@ const char* pk_status_string(pk_status s);
  * truncated to n bytes). Returns the full length of the message. */
 size_t pk_last_error(char* buf, size_t n);
 
+/* The same call under its longer name: copies the calling thread's last error detail into
+ * buf exactly as pk_last_error does and returns the message's full length. */
+size_t pk_last_error_detail(char* buf, size_t n);
+
 #ifdef __cplusplus
 }
 #endif

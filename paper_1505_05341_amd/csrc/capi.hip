@@ -873,4 +873,6 @@ size_t pk_last_error(char* buf, size_t n) {
   return g_last_error.size();
 }
 
+size_t pk_last_error_detail(char* buf, size_t n) { return pk_last_error(buf, n); }
+
 }  // extern "C"

@@ -44,7 +44,7 @@ class PkResult(ctypes.Structure):
 
 EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_result_doubles",
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
-           "pk_last_error", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
+           "pk_last_error", "pk_last_error_detail", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
            "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune",
            "pk_x_planes", "pk_stage_fft", "pk_stage_contract", "pk_hgrid_layout", "pk_zgroup"]
 
@@ -81,6 +81,8 @@ def load():
     lib.pk_status_string.restype = c_char_p
     lib.pk_last_error.argtypes = [ctypes.c_char_p, c_size_t]
     lib.pk_last_error.restype = c_size_t
+    lib.pk_last_error_detail.argtypes = [ctypes.c_char_p, c_size_t]
+    lib.pk_last_error_detail.restype = c_size_t
     lib.pk_workspace_size_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, P(c_size_t)]
     lib.pk_multipoles_batch.argtypes = [P(PkConfig), P(PkCatalog), P(PkCatalog), c_int32, c_int32, c_void_p, c_size_t,
                                         P(PkResult), P(c_int32), c_void_p]
@@ -95,7 +97,7 @@ def load():
     lib.pk_stage_name.restype = c_char_p
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
-            "pk_result_doubles", "pk_num_grids", "pk_status_string", "pk_last_error", "pk_stage_times",
+            "pk_result_doubles", "pk_num_grids", "pk_status_string", "pk_last_error", "pk_last_error_detail", "pk_stage_times",
             "pk_stage_name") else c_int32
     _lib = lib
     return lib
