@@ -307,6 +307,9 @@ struct XSwizzle {
   __device__ __forceinline__ int operator()(int i) const { return i ^ ((i >> 4) & 15); }
 };
 
+// Planes per band of the x pass's row order (see xpass_kernel).
+constexpr int kZBand = 8;
+
 // Waves per SIMD the registers are budgeted for (<= 64 VGPRs at 8): 8 up to N = 1024, i.e.
 // 4 blocks of 512 threads per CU (up to 512) or 2 of 1024 threads (at 1024), as the LDS
 // of the 15 gathered rows allows (measured 11% faster than 6 at 512, 14-30% than 4 at
@@ -342,11 +345,19 @@ __global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves
   // the hardware lane count instead of holding tid through the gather and the transform
   // (at N = 1024 with TSC that long-lived register was spilled to scratch, ~8 GB a launch)
   const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;
-  // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j walks
-  // the rows of the slab's planes [j xs/8, (j+1) xs/8) in order (xs = gridDim.y) and the
-  // source rows that neighbouring target rows share stay in that XCD's L2.
+  // Workgroups go to the 8 XCDs round-robin by linear id; remap so that XCD j takes the
+  // rows of the slab's planes [j xs/8, (j+1) xs/8) (xs = gridDim.y) and the source rows
+  // that neighbouring target rows share stay in that XCD's L2. Where the planes split into
+  // bands of kZBand, the XCD walks each band with y outer and z inner, so the rows of
+  // planes z - 1 and z + 1 are still in L2 when plane z needs them (a particle is fetched
+  // about once per band rather than once per plane that it reaches); else in plane order.
   const uint32_t lin = blockIdx.x + blockIdx.y * (uint32_t)N;
-  const uint32_t logical = (lin & 7u) * (uint32_t)(N * gridDim.y / 8) + (lin >> 3);
+  const uint32_t xcd_rows = (uint32_t)(N * gridDim.y / 8), l = lin >> 3;
+  uint32_t logical = (lin & 7u) * xcd_rows + l;
+  if (gridDim.y % (8 * kZBand) == 0) {
+    const uint32_t band = l / (uint32_t)(N * kZBand), r = l % (uint32_t)(N * kZBand);
+    logical = (lin & 7u) * xcd_rows + (band * kZBand + r % kZBand) * (uint32_t)N + r / kZBand;
+  }
   const int y = (int)(logical % N), zs = (int)(logical / N), z = a.z0 + zs;
 
   // source rows: the particles whose base cell (iy, iz) = (y - oy, z - oz) reach this row
