@@ -90,9 +90,9 @@ def plan_bytes(cfg, n_gal, n_ran, slabs=False):
     for kt in range(Kx // TK):
         M = math.isqrt(K * K - 1 - (kt * TK) ** 2)
         hstride += N * (2 * M + 1) * TK
-    G = {0: 1, 2: 7, 4: 22}[ell]
+    GK = {0: 1, 2: 6, 4: 15}[ell]   # stored x-transformed grids (power of rhat_z below 2)
     ngroups = {0: 1, 2: 4, 4: 9}[ell]
-    X = G * N * N * Kx * 8
+    X = GK * N * N * Kx * 8
     H = ngroups * hstride * 8
     Np = n_gal + n_ran
     out = {

@@ -197,7 +197,10 @@ int64_t pk_result_doubles(const pk_config* cfg);
 pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_catalog* ran,
                           void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Where pk_stage_xgrids leaves grid `m`: complex64 values X[z][y][kx] for z < x_planes
+/* Where pk_stage_xgrids leaves grid `m` (a monomial with a power of rhat_z below 2: only
+ * those are stored, 1, 6, 15 or 28 of the 1, 7, 22 or 50; any other monomial is an integer
+ * combination of them through rhat_x^2 + rhat_y^2 + rhat_z^2 = 1, which the y transform
+ * applies, and returns PK_EINVAL here): complex64 values X[z][y][kx] for z < x_planes
  * (pk_x_planes), y < N, kx < kx_count: the x-transformed (unnormalised,
  * e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at byte `offset` of the
  * workspace. At N = 2048 the values are stored tile-major, X[z][kx / 4][y][kx % 4]
@@ -246,12 +249,16 @@ pk_status pk_x_planes(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_
 
 /* Schedules of the column transforms (the FFTs along y and along z): the values each
  * thread holds, 16 (radices 16, 8, 4 at N = 512: fewer threads per transform) or 8
- * (radices 8, 8, 8: half the registers). A process-wide table keyed by (N, ell_max),
- * default 16 for the y pass and 8 for the z pass, read when a call plans its work (not thread-safe against
- * concurrent changes). Both schedules compute the same transform; results agree to FP32
- * rounding. At N = 2048 only the 8-value schedule is built (16 values per thread would
- * need more than 256 registers): it is the only value reported and accepted there.
- * PK_EINVAL for an unsupported N or ell_max or values other than 8 and 16. */
+ * (radices 8, 8, 8: half the registers). With 8 values the y pass sums up to 6 z-power
+ * groups per launch, so each stored x-transformed grid is loaded once per parity of the
+ * power of tz (ell_max <= 4); with 16 values its registers hold 3 groups, and grids that
+ * several such sets need are loaded once per set. A process-wide table keyed by
+ * (N, ell_max), default 8 for both passes, read when a call plans its work (not
+ * thread-safe against concurrent changes). Both schedules compute the same transform;
+ * results agree to FP32 rounding. At N = 2048 only the 8-value schedule is built (16
+ * values per thread would need more than 256 registers): it is the only value reported
+ * and accepted there. PK_EINVAL for an unsupported N or ell_max or values other than 8
+ * and 16. */
 pk_status pk_set_schedule(int32_t N, int32_t ell_max, int32_t y_values, int32_t z_values);
 pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t* z_values);
 

@@ -139,7 +139,8 @@ def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace |
 def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
     """Runs up to the fused assignment + x transform of the first slab of planes and
     returns (workspace tensor, layout), layout[m] = (byte offset, kx_count, planes) of grid
-    m (complex64 X[z][y][kx] for z < planes)."""
+    m (complex64 X[z][y][kx] for z < planes) for every stored grid: the monomials with a
+    power of rhat_z below 2 (the others follow from them, rhat_z^2 = 1 - rhat_x^2 - rhat_y^2)."""
     import torch
     lib = native.load()
     c = native.make_config(cfg)
@@ -151,6 +152,8 @@ def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: W
     layout = {}
     planes = native.x_planes(cfg, gal.n, ran.n)
     for m in range(native.num_grids(c.ell_max)):
+        if native.monomial(m)[2] > 1:
+            continue
         off = ctypes.c_size_t()
         kx = ctypes.c_int32()
         native.check(lib.pk_xgrid_layout(ctypes.byref(c), gal.n, ran.n, m, ctypes.byref(off), ctypes.byref(kx)))

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "basis.hpp"
 #include "plan.hpp"
 
 namespace pk {
@@ -53,9 +54,10 @@ static int auto_slab(int N, int G, int Kx) {
 }
 
 // Schedules of the column transforms (values per thread of the y and z passes), per
-// (N, ell_max): set by pk_set_schedule or the autotuner; 0 = not set, meaning 16 for the
-// y pass and 8 for the z pass (whose prefetched column does not fit the registers of the
-// 16-value schedule).
+// (N, ell_max): set by pk_set_schedule or the autotuner; 0 = not set, meaning 8 for both:
+// the y pass then sums up to 6 z-power groups at once (with 16 values only 3 fit its
+// registers, so grids shared by more groups are loaded more than once), and the z pass's
+// prefetched column does not fit the registers of the 16-value schedule.
 struct Schedule {
   int y, z;
 };
@@ -65,6 +67,65 @@ static int log2_of(int N) {
   int l = 0;
   while ((1 << l) < N) ++l;
   return l;
+}
+
+// Sets of the y pass (see YSetTable) for groups of at most gmax: the groups of each parity
+// of c in order, gmax at a time; a set's members are the gathered grids, in gathered order,
+// that carry a term of one of its groups. A member (a, b, c) of group (n, c) with weight
+// coef contributes coef w tx^a ty^b to gathered grid j, w the integer weight of j in the
+// identity's expansion of rhat^(a,b,c) (basis.hpp; 1 if (a, b, c) is gathered itself).
+// At most 6 sets, 56 members and 119 terms (ell_max = 6 with sets of 3): within the
+// table's bounds for every ell_max.
+static void build_ysets(const GroupTable& gt, int ell, int gmax, YSetTable* yt) {
+  memset(yt, 0, sizeof(*yt));
+  const int GK = kept_count(ell), ND = dep_count(ell);
+  int kidx[kMaxGrids], didx[kMaxGrids];
+  for (int m = 0; m < kMaxGrids; ++m) kidx[m] = didx[m] = -1;
+  for (int j = 0; j < GK; ++j) kidx[kept_monomial(j)] = j;
+  for (int d = 0; d < ND; ++d) didx[dep_monomial(d)] = d;
+  int nm = 0, nt = 0;
+  for (int par = 0; par < 2; ++par) {
+    int gs[kMaxGroups], ng = 0;
+    for (int g = 0; g < gt.ngroups; ++g)
+      if (gt.c[g] % 2 == par) gs[ng++] = g;
+    for (int i0 = 0; i0 < ng; i0 += gmax) {
+      const int s = yt->nsets++;
+      const int k = ng - i0 < gmax ? ng - i0 : gmax;
+      yt->ngroups[s] = (int8_t)k;
+      for (int q = 0; q < k; ++q) yt->group[s][q] = (int8_t)gs[i0 + q];
+      yt->mem0[s] = (int16_t)nm;
+      for (int j = 0; j < GK; ++j) {
+        const int t0 = nt;
+        for (int q = 0; q < k; ++q) {
+          const int g = gs[i0 + q];
+          for (int u = 0; u < gt.count[g]; ++u) {
+            const int m = gt.grid[g][u];
+            int w = 0;
+            if (kidx[m] >= 0) {
+              w = kidx[m] == j ? 1 : 0;
+            } else {
+              const int d = didx[m];
+              for (int v = 0; v < dep_terms(d); ++v)
+                if (dep_kept(d, v) == j) w += (int)dep_coef(d, v);
+            }
+            if (w == 0) continue;
+            yt->tslot[nt] = (int8_t)q;
+            yt->ta[nt] = (int8_t)gt.a[g][u];
+            yt->tb[nt] = (int8_t)gt.b[g][u];
+            yt->tcoef[nt] = gt.coef[g][u] * (float)w;
+            ++nt;
+          }
+        }
+        if (nt > t0) {
+          yt->mgrid[nm] = (int8_t)j;
+          yt->term0[nm] = (int16_t)t0;
+          ++nm;
+        }
+      }
+    }
+  }
+  yt->mem0[yt->nsets] = (int16_t)nm;
+  yt->term0[nm] = (int16_t)nt;
 }
 
 pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* plan, const char** why) {
@@ -106,11 +167,12 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
     return fail(PK_EINVAL, "x_planes must be 0 (automatic) or a power of two <= N");
 
   p.G = num_grids_for(p.ell_max);
+  p.GK = kept_count(p.ell_max);
   p.K = p.nbins * p.dn;
   p.TK = p.N >= 2048 ? 4 : (p.N >= 1024 ? 8 : (p.N / 2 < 16 ? p.N / 2 : 16));  // tile_cols<N>() of the FFT passes
   p.Kx = ((p.K + p.TK - 1) / p.TK) * p.TK;
   p.nkt = p.Kx / p.TK;
-  p.xs = cfg->x_planes ? cfg->x_planes : auto_slab(p.N, p.G, p.Kx);
+  p.xs = cfg->x_planes ? cfg->x_planes : auto_slab(p.N, p.GK, p.Kx);
   p.xr = p.N / p.xs < 2 ? 1 : 2;  // X holds two slabs (double buffer) when there are several
   // tiles: the y pass keeps |ky| <= M(kt) with kx0^2 + ky^2 < K^2, kx0 = kt * TK
   int64_t reg = 0, items = 0;
@@ -128,7 +190,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.z_items = items;
   p.z_blocks = (int)(items < 512 ? items : 512);
   const Schedule sc = g_sched[log2_of(p.N)][p.ell_max / 2];
-  p.col_e[0] = p.N >= 2048 ? 8 : (sc.y ? sc.y : 16);  // only the 8-value schedule is built at 2048
+  p.col_e[0] = p.N >= 2048 ? 8 : (sc.y ? sc.y : 8);  // only the 8-value schedule is built at 2048
   p.col_e[1] = p.N >= 2048 ? 8 : (sc.z ? sc.z : 8);
 
   // groups (n, c) and their members (grid index, a, b, multinomial weight)
@@ -153,16 +215,8 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
     }
   }
 
-  gt.nmem = 0;
-  for (int g = 0; g < gt.ngroups; ++g) {
-    for (int s = gt.count[g] - 1; s >= 0; --s) {
-      gt.mgrid[gt.nmem] = gt.grid[g][s];
-      gt.ma[gt.nmem] = gt.a[g][s];
-      gt.mcoef[gt.nmem] = gt.coef[g][s];
-      ++gt.nmem;
-    }
-    gt.mend[g] = gt.nmem;
-  }
+  build_ysets(gt, p.ell_max, kYSetGroups, &p.ysets[0]);
+  build_ysets(gt, p.ell_max, 3, &p.ysets[1]);
 
   const int nl = p.ell_max / 2 + 1;
   p.result_doubles = result_size(p.nbins, nl);
@@ -179,7 +233,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_tw = take(sizeof(float) * 2 * p.N);
   p.off_invw2 = take(sizeof(float) * p.N);
   p.off_alias = take(sizeof(float) * p.N);
-  p.off_tables = take(sizeof(GroupTable) + sizeof(TileTable));
+  p.off_tables = take(tables_bytes());
   p.off_rowcnt = take(sizeof(uint32_t) * ((size_t)p.N * sort_blocks(n_gal + n_ran) + 1));  // plane histograms
   p.off_rowoff = take(sizeof(uint32_t) * (nrow + 1));
   p.off_rowhist = take(sizeof(uint32_t) * ((size_t)nrow * kRowHistParts + 1));  // per-part row counts
@@ -187,7 +241,7 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.off_tmp = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
   p.off_rowkey = take(sizeof(uint16_t) * (size_t)(n_gal + n_ran));
   p.off_sorted = take(sizeof(float) * 4 * (size_t)(n_gal + n_ran));
-  p.off_X = take(sizeof(float) * 2 * (size_t)p.G * p.xr * p.xs * p.N * p.Kx);  // xr slots of xs planes
+  p.off_X = take(sizeof(float) * 2 * (size_t)p.GK * p.xr * p.xs * p.N * p.Kx);  // xr slots of xs planes
   p.off_H = take(sizeof(float) * 2 * (size_t)gt.ngroups * p.H_group_stride);
   p.off_zpart = take(sizeof(double) * kNumSums * (size_t)p.z_blocks * p.nbins);
   p.off_result = take(sizeof(double) * (size_t)p.result_doubles);
@@ -513,7 +567,7 @@ pk_status pk_get_schedule(int32_t N, int32_t ell_max, int32_t* y_values, int32_t
   if (!schedule_key_ok(N, ell_max)) return fail(PK_EINVAL, "unsupported N or ell_max");
   if (!y_values || !z_values) return fail(PK_EINVAL, "null output pointer");
   const Schedule sc = g_sched[log2_of(N)][ell_max / 2];
-  *y_values = N >= 2048 ? 8 : (sc.y ? sc.y : 16);
+  *y_values = N >= 2048 ? 8 : (sc.y ? sc.y : 8);
   *z_values = N >= 2048 ? 8 : (sc.z ? sc.z : 8);
   return PK_OK;
 }
@@ -805,7 +859,11 @@ pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, in
   if (st != PK_OK) return st;
   if (m < 0 || m >= p.G) return fail(PK_EINVAL, "grid index out of range");
   if (!offset || !kx_count) return fail(PK_EINVAL, "null output pointer");
-  *offset = p.off_X + sizeof(float) * 2 * (size_t)m * p.xr * p.xs * p.N * p.Kx;
+  int j = -1;
+  for (int i = 0; i < p.GK; ++i)
+    if (kept_monomial(i) == m) j = i;
+  if (j < 0) return fail(PK_EINVAL, "grid not stored: its power of rhat_z is 2 or more (it follows from the stored ones)");
+  *offset = p.off_X + sizeof(float) * 2 * (size_t)j * p.xr * p.xs * p.N * p.Kx;
   *kx_count = p.Kx;
   return PK_OK;
 }

@@ -12,6 +12,10 @@ namespace pk {
 constexpr int kMaxGrids = 50;       // 1 + 6 + 15 + 28 monomial grids (ell_max = 6)
 constexpr int kMaxGroups = 16;      // z-power groups: 1 + 3 + 5 + 7
 constexpr int kMaxMembers = 7;
+constexpr int kYSetGroups = 6;      // z-power groups one y-pass block sums at once (8-value schedule)
+constexpr int kMaxYSets = 6;        // sets of groups per schedule (ell_max = 6 with sets of 3)
+constexpr int kMaxYMembers = 64;    // gathered grids loaded by all sets of one schedule
+constexpr int kMaxYTerms = 128;     // weight terms of all sets of one schedule
 constexpr int kMaxTiles = 256;      // kx tiles: 16 columns up to N = 512, 8 at 1024, 4 at 2048
 constexpr int kStatsBlocks = 2048;  // blocks of the catalogue-scalar reduction
 constexpr int kScanChunk = 4096;    // counters per scan block
@@ -61,13 +65,26 @@ struct GroupTable {
   int a[kMaxGroups][kMaxMembers];
   int b[kMaxGroups][kMaxMembers];
   float coef[kMaxGroups][kMaxMembers];
-  // the same members flattened in the order the y pass takes them (group by group,
-  // largest power of y first); group g ends before member mend[g]
-  int nmem;
-  int mgrid[kMaxGrids];
-  int ma[kMaxGrids];
-  float mcoef[kMaxGrids];
-  int mend[kMaxGroups];
+};
+
+// The groups written from the gathered grids alone. X holds only the monomials with a
+// power of rhat_z below 2; a member (a, b, c) of group (n, c) with c >= 2 is the integer
+// combination of gathered monomials that rhat_z^2 = 1 - rhat_x^2 - rhat_y^2 gives, so
+//   H_(n,c) = sum_j Q_(j,n,c)(tx, ty) Y_j,  Q = sum of terms coef tx^a ty^b,
+// over gathered grids j (no rhat_z for even c, one power for odd c). A set is up to
+// kYSetGroups (8-value column schedule) or 3 (16-value schedule, whose registers hold
+// fewer sums) groups of one parity of c: one y-pass launch per set loads each of the set's
+// grids once and adds it, with its terms, into every group of the set.
+struct YSetTable {
+  float tcoef[kMaxYTerms];                // weight of a term
+  int32_t nsets;
+  int16_t mem0[kMaxYSets + 1];            // members of set s: [mem0[s], mem0[s + 1])
+  int16_t term0[kMaxYMembers + 1];        // terms of member i: [term0[i], term0[i + 1])
+  int8_t ngroups[kMaxYSets];              // groups in set s
+  int8_t group[kMaxYSets][kYSetGroups];   // H group of slot k of set s
+  int8_t mgrid[kMaxYMembers];             // X grid (gathered index) of a member
+  int8_t tslot[kMaxYTerms];               // slot (group of the set) of a term
+  int8_t ta[kMaxYTerms], tb[kMaxYTerms];  // powers of tx and ty of a term
 };
 
 // Tile table of the y and z passes: per kx tile the largest |ky| kept (M), the
@@ -84,7 +101,8 @@ struct Plan {
   double box_min[3], L, observer[3];
   int64_t n_gal, n_ran;
   // derived
-  int G;          // LOS-weighted grids: 1, 7, 22
+  int G;          // LOS-weighted grids: 1, 7, 22, 50
+  int GK;         // of them gathered and stored in X (power of rhat_z below 2): 1, 6, 15, 28
   int K;          // nbins * dn: modes with |n| < K are binned
   int TK;         // kx columns per FFT tile
   int Kx;         // kx columns kept after the x transform (multiple of TK, <= N/2)
@@ -95,6 +113,7 @@ struct Plan {
   int col_e[2];   // values per thread of the column transforms of the y and z passes (8 or 16)
   int64_t z_items;
   GroupTable groups;
+  YSetTable ysets[2];  // y-pass sets of the 8- and 16-value schedules
   TileTable tiles;
   // workspace offsets (bytes)
   size_t off_scalars, off_partials, off_flags, off_tw, off_invw2, off_alias, off_tables;
@@ -103,6 +122,11 @@ struct Plan {
   size_t H_group_stride;   // float2 elements per group in H
   int64_t result_doubles;
 };
+
+// Workspace offsets of the device tables (from off_tables).
+constexpr size_t ysets_offset(int schedule) { return (size_t)schedule * sizeof(YSetTable); }
+constexpr size_t tiles_offset() { return 2 * sizeof(YSetTable); }
+constexpr size_t tables_bytes() { return 2 * sizeof(YSetTable) + sizeof(TileTable); }
 
 int sort_blocks(int64_t ntot);
 pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* plan, const char** why);

@@ -2,9 +2,9 @@
 // Sec. 4 for the assignment).
 //
 // One block owns one target grid row (y, z) of the 1, 7, 22 or 50 monomial grids
-// F rhat^m. Only the 1, 6, 15 or 28 monomials with a power of rhat_z below 2 are gathered and
-// transformed; the others follow exactly from rhat_x^2 + rhat_y^2 + rhat_z^2 = 1 and are
-// written as combinations of the transformed rows (basis.hpp). The particles whose
+// F rhat^m. Only the 1, 6, 15 or 28 monomials with a power of rhat_z below 2 are gathered,
+// transformed and stored; the others follow exactly from rhat_x^2 + rhat_y^2 + rhat_z^2 = 1
+// and enter the y pass as combinations of the stored rows (basis.hpp). The particles whose
 // stencil reaches the row are those of a few source rows, which the counting sort made
 // contiguous. They are processed in chunks:
 //   1. each particle's own line of sight rhat = (x - observer)/|x - observer|, its
@@ -330,8 +330,7 @@ constexpr size_t xpass_tw_offset() {
 template <int N, int ASSIGN, int ELL>
 __global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves_per_eu(xpass_waves<N, ELL>(), 8))) void xpass_kernel(const float4* __restrict__ sorted, const uint32_t* __restrict__ rowoff,
                                                     const float2* __restrict__ tw, float2* __restrict__ X, XArgs a) {
-  constexpr int GK = kept_count(ELL);   // gathered and transformed rows
-  constexpr int ND = dep_count(ELL);    // rows written as their combinations
+  constexpr int GK = kept_count(ELL);   // gathered, transformed and stored rows
   constexpr int NP = (GK + 1) / 2;
   constexpr int S = ASSIGN == PK_CIC ? 2 : 3;
   constexpr int O0 = ASSIGN == PK_CIC ? 0 : -1;
@@ -403,11 +402,9 @@ __global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves
     for (int e = 0; e < F::E; ++e) Tq[XSwizzle()(F::out_index(t, e))] = d[e];
   }
   __syncthreads();
-  // Thread kx < Kx (Kx <= N / 2 <= block size) unpacks each kept spectrum at kx once,
-  // stores it at its monomial index and adds it into the rows with a power of rhat_z of 2
-  // or more, which the identity of basis.hpp makes from the kept ones. Rows (2q, 2q+1) were
-  // transformed as one complex row Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and
-  // X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
+  // Thread kx < Kx (Kx <= N / 2 <= block size) unpacks each gathered spectrum at kx and
+  // stores it at its gathered index. Rows (2q, 2q+1) were transformed as one complex row
+  // Z, so X_2q[k] = (Z[k] + conj Z[N-k]) / 2 and X_2q+1[k] = -i (Z[k] - conj Z[N-k]) / 2.
   const int Kx = a.Kx;
   const int kx = wave0 + (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   if (kx < Kx) {
@@ -417,38 +414,16 @@ __global__ __launch_bounds__((XGeom<N, ASSIGN>::NT)) __attribute__((amdgpu_waves
     else
       o = ((size_t)(a.pbase + zs) * N + y) * (size_t)Kx + kx;
     const int ik = XSwizzle()(kx), im = XSwizzle()((N - kx) & (N - 1));
-    // the grid stride is opaque here: otherwise the compiler forms all GK + ND products
-    // with it up front and holds them in (spilled) scalar registers through the kernel
+    // the grid stride is opaque here: otherwise the compiler forms all GK products with
+    // it up front and holds them in (spilled) scalar registers through the kernel
     int64_t gs = a.grid_stride;
     asm volatile("" : "+s"(gs));
-    // one row pair at a time: its two kept rows are stored and added into the sums of
-    // the dependent rows, so only those ND sums stay live (not all GK kept values)
-    float2 v[ND > 0 ? ND : 1];
-#pragma unroll
-    for (int dd = 0; dd < ND; ++dd) v[dd] = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int qq = 0; qq < NP; ++qq) {
       const float2 zk = T[qq * N + ik], zm = T[qq * N + im];
-      const float2 xp[2] = {make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)),
-                            make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x))};
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = 2 * qq + h;
-        if (j < GK) {
-          X[(size_t)kept_monomial(j) * gs + o] = xp[h];
-#pragma unroll
-          for (int dd = 0; dd < ND; ++dd)
-#pragma unroll
-            for (int u = 0; u < dep_terms(dd); ++u)
-              if (dep_kept(dd, u) == j) {
-                v[dd].x += dep_coef(dd, u) * xp[h].x;
-                v[dd].y += dep_coef(dd, u) * xp[h].y;
-              }
-        }
-      }
+      X[(size_t)(2 * qq) * gs + o] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      if (2 * qq + 1 < GK) X[(size_t)(2 * qq + 1) * gs + o] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
     }
-#pragma unroll
-    for (int dd = 0; dd < ND; ++dd) X[(size_t)dep_monomial(dd) * gs + o] = v[dd];
   }
 }
 

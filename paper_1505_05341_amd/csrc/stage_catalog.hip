@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void init_kernel(int N, int assign, int* flags
 // Copies the group and tile tables into the workspace, passed by value as 32-bit words
 // in pieces of at most 2 KB of kernel arguments (so that a captured graph holds them).
 constexpr int kTableChunkWords = 512;
-constexpr int kTableWords = (int)((sizeof(GroupTable) + sizeof(TileTable) + 3) / 4);
+constexpr int kTableWords = (int)((tables_bytes() + 3) / 4);
 struct TableChunk {
   uint32_t w[kTableChunkWords];
 };
@@ -50,8 +50,9 @@ __global__ __launch_bounds__(256) void copy_tables_kernel(const TableChunk c, in
 hipError_t launch_init(const Plan& p, char* ws, hipStream_t s) {
   uint32_t words[kTableWords];
   memset(words, 0, sizeof(words));
-  memcpy(words, &p.groups, sizeof(GroupTable));
-  memcpy(reinterpret_cast<char*>(words) + sizeof(GroupTable), &p.tiles, sizeof(TileTable));
+  memcpy(reinterpret_cast<char*>(words) + ysets_offset(0), &p.ysets[0], sizeof(YSetTable));
+  memcpy(reinterpret_cast<char*>(words) + ysets_offset(1), &p.ysets[1], sizeof(YSetTable));
+  memcpy(reinterpret_cast<char*>(words) + tiles_offset(), &p.tiles, sizeof(TileTable));
   for (int w0 = 0; w0 < kTableWords; w0 += kTableChunkWords) {
     const int n = kTableWords - w0 < kTableChunkWords ? kTableWords - w0 : kTableChunkWords;
     TableChunk c;

@@ -4,9 +4,12 @@
 // H is stored in tiles of TKH kx columns (tile_cols): for each group, tile and z, the
 // rows |ky| <= M(tile) of TKH complex values.
 // y pass: one block owns TK kx columns (a whole H tile, or half of one at N = 512 and
-//   1024) at one z. For every monomial grid it loads the N x TK tile (TK complex values
-//   per row, coalesced), transforms along y and multiplies by coef_m tx^a ty^b; the
-//   grids of one group (degree n, power c of z) are summed in registers, so each group
+//   1024) at one z and one set of groups of one parity of c. X holds only the gathered
+//   monomials (power of rhat_z below 2); a group's other members are combinations of them
+//   (rhat_z^2 = 1 - rhat_x^2 - rhat_y^2), so H_{n,c} = sum_j Q_j(tx, ty) Y_j over gathered
+//   grids j with polynomial weights Q_j. For each gathered grid of the set the block loads
+//   the N x TK tile (TK complex values per row, coalesced), transforms along y and adds it
+//   with its weights into every group of the set, whose sums stay in registers; each group
 //   leaves a single grid H_{n,c}. Only the rows with kx0^2 + ky^2 < K^2 are stored
 //   (kx0 = the H tile's smallest kx).
 // z pass: a persistent block walks (kx tile, ky) columns (a whole H tile, or half of
@@ -32,7 +35,7 @@ struct YArgs {
   int pbase;              // plane of X that holds plane z0
   int64_t x_grid_stride;  // xr xs N Kx
   int64_t h_group_stride;
-  const GroupTable* gt;   // device copies (dynamic indexing of by-value kernel
+  const YSetTable* yt;    // device copies (dynamic indexing of by-value kernel
   const TileTable* tt;    // arguments would push them to scratch)
 };
 
@@ -110,101 +113,147 @@ __device__ __forceinline__ void load_member(const float2* __restrict__ X, const 
   }
 }
 
-template <int N, int TK, int EC, int TKH>
+// One set of z-power groups (YSetTable) for TK kx columns at one z: every member (a
+// gathered grid of the set) is loaded once, transformed along y, and added into each group
+// of the set it has terms in, with weight sum coef tx^a ty^b; the NGS group sums stay in
+// registers until the end.
+template <int N, int TK, int EC, int TKH, int NGS>
 __global__ __launch_bounds__((TK * Fft<N, EC>::T)) void ypass_kernel(const float2* __restrict__ X, float2* __restrict__ H,
-                                                                  const float2* __restrict__ tw, const YArgs a) {
+                                                                  const float2* __restrict__ tw, const YArgs a,
+                                                                  const int set) {
   static_assert(TKH % TK == 0, "a y tile is a part of an H tile");
   using F = Fft<N, EC>;
   extern __shared__ float2 T[];
-  // The flattened member table and the twiddles, in LDS: loads of global memory retire
+  // The set's members and terms and the twiddles, in LDS: loads of global memory retire
   // in order, so reading either from global memory inside a transform would also wait
   // for the next member's tile, which is in flight meanwhile.
   float2* twl = T + TK * N;
-  __shared__ int s_grid[kMaxGrids], s_pa[kMaxGrids], s_end[kMaxGroups];
-  __shared__ float s_coef[kMaxGrids];
+  __shared__ int s_grid[kMaxYMembers], s_t0[kMaxYMembers + 1], s_term[kMaxYTerms], s_group[kYSetGroups];
+  __shared__ float s_coef[kMaxYTerms];
   const int tid0 = threadIdx.x;
   const uint32_t nblk = gridDim.x * gridDim.y;
   const uint32_t lb = xcd_group(blockIdx.x + blockIdx.y * gridDim.x, nblk);
   const int kt = (int)(lb % gridDim.x), zs = (int)(lb / gridDim.x), z = a.z0 + zs;
-  const GroupTable& gt = *a.gt;
-  const int nmem = gt.nmem, ngroups = gt.ngroups;
-  for (int i = tid0; i < nmem; i += blockDim.x) {
-    s_grid[i] = gt.mgrid[i];
-    s_pa[i] = gt.ma[i];
-    s_coef[i] = gt.mcoef[i];
+  const YSetTable& yt = *a.yt;
+  const int m0 = yt.mem0[set], nmem = yt.mem0[set + 1] - m0, ngs = yt.ngroups[set];
+  const int q0 = yt.term0[m0], nterm = yt.term0[m0 + nmem] - q0;
+  for (int i = tid0; i < nmem; i += blockDim.x) s_grid[i] = yt.mgrid[m0 + i];
+  for (int i = tid0; i <= nmem; i += blockDim.x) s_t0[i] = yt.term0[m0 + i] - q0;
+  for (int i = tid0; i < nterm; i += blockDim.x) {
+    s_term[i] = yt.tslot[q0 + i] | (yt.ta[q0 + i] << 8) | (yt.tb[q0 + i] << 16);  // slot, a, b
+    s_coef[i] = yt.tcoef[q0 + i];
   }
-  for (int i = tid0; i < ngroups; i += blockDim.x) s_end[i] = gt.mend[i];
+  for (int i = tid0; i < ngs; i += blockDim.x) s_group[i] = yt.group[set][i];
   for (int i = tid0; i < N; i += blockDim.x) twl[i] = tw[i];
   // the H tile (TKH columns) this block's TK columns belong to, and their offset in it
   const int kth = kt * TK / TKH, ch = kt * TK - kth * TKH;
   const int M = a.tt->M[kth];
   const int64_t regoff = a.tt->regoff[kth];
   const int nslot = 2 * M + 1;
-  // the EC = 16 schedule keeps the ty of its values in registers
+  // ty of each of the thread's output values, and tx of its column
   float tyv[F::E];
 #pragma unroll
   for (int e = 0; e < F::E; ++e) tyv[e] = (float)signed_freq<N>(F::out_index(tid0 / TK, e)) * (2.0f / N);
+  const float tx = (float)(kt * TK + tid0 % TK) * (2.0f / N);
   __syncthreads();
-  // member j + 1 is loaded while member j is transformed
-  float2 nd[F::E];
-  load_member<N, TK, EC>(X, a, s_grid[0], zs, kt, tid0, nd);
-  int j = 0;
-  for (int g = 0; g < ngroups; ++g) {
-    // Horner in ty over the members, whose powers of y run 0, 1, .., n - c:
-    // acc <- acc ty + coef tx^a Y_(a,b,c), taken from the largest b down.
-    float2 acc[F::E];
+  float2 acc[NGS][F::E];
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) acc[e] = make_float2(0.0f, 0.0f);
-    const int jend = s_end[g];
-    for (; j < jend; ++j) {
+  for (int g = 0; g < NGS; ++g)
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) acc[g][e] = make_float2(0.0f, 0.0f);
+  {
+    // member j + 1 is loaded while member j is transformed
+    float2 nd[F::E];
+    load_member<N, TK, EC>(X, a, s_grid[0], zs, kt, tid0, nd);
+    for (int j = 0; j < nmem; ++j) {
       float2 d[F::E];
 #pragma unroll
       for (int e = 0; e < F::E; ++e) d[e] = nd[e];
       if (j + 1 < nmem) load_member<N, TK, EC>(X, a, s_grid[j + 1], zs, kt, tid0, nd);
       const int tid = col_hide<EC>(tid0);
-      const int c = tid % TK, t = tid / TK;
-      const int kx = kt * TK + c;
-      F::run(d, t, twl, T, ColSlot<TK>{c});
-      const float fx = s_coef[j] * ipow((float)kx * (2.0f / N), s_pa[j]);
+      F::run(d, tid / TK, twl, T, ColSlot<TK>{tid % TK});
+      // the member's terms: coef tx^a ty^b into group slot s (block-uniform: scalar branches)
+      const int qe = __builtin_amdgcn_readfirstlane(s_t0[j + 1]);
+      for (int q = __builtin_amdgcn_readfirstlane(s_t0[j]); q < qe; ++q) {
+        const int term = __builtin_amdgcn_readfirstlane(s_term[q]);
+        const int s = term & 0xff, pa = (term >> 8) & 0xff, pb = term >> 16;
+        float k = s_coef[q];
+        for (int i = 0; i < pa; ++i) k *= tx;
+        float w[F::E];
 #pragma unroll
-      for (int e = 0; e < F::E; ++e) {
-        const float ty = EC == 8 ? (float)signed_freq<N>(F::out_index(t, e)) * (2.0f / N) : tyv[e];
-        acc[e].x = acc[e].x * ty + fx * d[e].x;
-        acc[e].y = acc[e].y * ty + fx * d[e].y;
+        for (int e = 0; e < F::E; ++e) w[e] = k;
+        for (int i = 0; i < pb; ++i)
+#pragma unroll
+          for (int e = 0; e < F::E; ++e) w[e] *= tyv[e];
+#pragma unroll
+        for (int g = 0; g < NGS; ++g) {
+          if (g == s) {
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) {
+              acc[g][e].x += w[e] * d[e].x;
+              acc[g][e].y += w[e] * d[e].y;
+            }
+          }
+        }
       }
     }
-    const int c = tid0 % TK, t = tid0 / TK;
-    float2* __restrict__ dst = H + (size_t)g * a.h_group_stride + regoff + (size_t)z * nslot * TKH + ch + c;
+  }
+  const int c = tid0 % TK, t = tid0 / TK;
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) {
-      const int ky = signed_freq<N>(F::out_index(t, e));
-      if (ky >= -M && ky <= M) dst[(size_t)(ky + M) * TKH] = acc[e];
+  for (int g = 0; g < NGS; ++g) {
+    if (g < ngs) {
+      float2* __restrict__ dst =
+          H + (size_t)s_group[g] * a.h_group_stride + regoff + (size_t)z * nslot * TKH + ch + c;
+#pragma unroll
+      for (int e = 0; e < F::E; ++e) {
+        const int ky = signed_freq<N>(F::out_index(t, e));
+        if (ky >= -M && ky <= M) dst[(size_t)(ky + M) * TKH] = acc[g][e];
+      }
     }
   }
 }
 
+// Register sums per schedule: the 8-value schedule takes sets of up to 6 groups (built as
+// 1, 3 or 6 slots) up to N = 512, the 16-value one sets of up to 3 (1 or 3 slots). From
+// N = 1024 on the 8-value schedule also takes the sets of up to 3: at 1024 the 6-slot
+// kernel (~167 registers) leaves one 512-thread block per CU, whose barriers in the
+// four-stage transform then stall the CU (32.9 ms against 29.8 ms with sets of 3 and two
+// blocks per CU, although sets of 3 load 19 grids instead of 15); at 2048, whose
+// 1024-thread blocks cap a thread at 128 registers, 6 slots would spill. At 512 the sets of
+// 6 take 3.10 ms against 3.50 ms for the G member grids of the full basis.
+template <int N, int TK, int EC, int TKH, int NGS>
+static void launch_yset(const Plan& p, char* ws, hipStream_t s, const YArgs& a, int set) {
+  const size_t shmem = (size_t)(TK + 1) * N * sizeof(float2);  // column tile + twiddles
+  const int ntiles = p.nkt * (TKH / TK);                      // y tiles: Kx / TK
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, EC, TKH, NGS>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  hipLaunchKernelGGL((ypass_kernel<N, TK, EC, TKH, NGS>), dim3(ntiles, p.xs), dim3(TK * Fft<N, EC>::T), shmem, s,
+                     at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a, set);
+}
+
 template <int N, int TK, int TKH>
 static hipError_t launch_y2(const Plan& p, char* ws, hipStream_t s, int z0, int pbase) {
+  const bool ec8 = N >= 2048 || p.col_e[0] == 8;
+  const int sched = (ec8 && N < 1024) ? 0 : 1;  // set table: up to 6 groups, or up to 3
   YArgs a;
   a.Kx = p.Kx;
   a.z0 = z0;
   a.pbase = pbase;
   a.x_grid_stride = (int64_t)p.xr * p.xs * p.N * p.Kx;
   a.h_group_stride = (int64_t)p.H_group_stride;
-  a.gt = at<const GroupTable>(ws, p.off_tables);
-  a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
-  const size_t shmem = (size_t)(TK + 1) * N * sizeof(float2);  // column tile + twiddles
-  const int ntiles = p.nkt * (TKH / TK);                      // y tiles: Kx / TK
-  if (N >= 2048 || p.col_e[0] == 8) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 8, TKH>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 8, TKH>), dim3(ntiles, p.xs), dim3(TK * Fft<N, 8>::T), shmem, s,
-                       at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
-  } else if constexpr (N < 2048) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&ypass_kernel<N, TK, 16, TKH>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((ypass_kernel<N, TK, 16, TKH>), dim3(ntiles, p.xs), dim3(TK * Fft<N, 16>::T), shmem, s,
-                       at<const float2>(ws, p.off_X), at<float2>(ws, p.off_H), at<const float2>(ws, p.off_tw), a);
+  a.yt = at<const YSetTable>(ws, p.off_tables + ysets_offset(sched));
+  a.tt = at<const TileTable>(ws, p.off_tables + tiles_offset());
+  const YSetTable& yt = p.ysets[sched];
+  for (int set = 0; set < yt.nsets; ++set) {
+    const int ng = yt.ngroups[set];
+    if (ec8) {
+      if (ng <= 1) launch_yset<N, TK, 8, TKH, 1>(p, ws, s, a, set);
+      else if (ng <= 3) launch_yset<N, TK, 8, TKH, 3>(p, ws, s, a, set);
+      else if constexpr (N < 1024) launch_yset<N, TK, 8, TKH, 6>(p, ws, s, a, set);
+    } else if constexpr (N < 2048) {
+      if (ng <= 1) launch_yset<N, TK, 16, TKH, 1>(p, ws, s, a, set);
+      else launch_yset<N, TK, 16, TKH, 3>(p, ws, s, a, set);
+    }
   }
   return hipGetLastError();
 }
@@ -572,7 +621,7 @@ static hipError_t launch_z2(const Plan& p, char* ws, hipStream_t s) {
   a.nkt = p.nkt;
   a.h_group_stride = (int64_t)p.H_group_stride;
   a.n_items = p.z_items * HP;
-  a.tt = at<const TileTable>(ws, p.off_tables + sizeof(GroupTable));
+  a.tt = at<const TileTable>(ws, p.off_tables + tiles_offset());
   switch (p.ell_max) {
     case 0: return launch_z3<N, TK, 0, HP>(p, ws, a, s);
     case 2: return launch_z3<N, TK, 2, HP>(p, ws, a, s);

@@ -28,7 +28,7 @@ def test_byte_model_matches_the_library_workspace():
         full = native.workspace_size(cfg, 0, 10)
         nox = native.workspace_size(dict(cfg, x_planes=1), 0, 10)   # two 1-plane slots of X
         assert full - nox == X - 2 * X // N, (N, full - nox, X)
-        assert H > 0 and X == 22 * N * N * (-(-nbins * dn // (16 if N <= 512 else 8)) * (16 if N <= 512 else 8)) * 8
+        assert H > 0 and X == 15 * N * N * (-(-nbins * dn // (16 if N <= 512 else 8)) * (16 if N <= 512 else 8)) * 8
     # slabs: the x and y transforms are timed as one stage
     s = bench.plan_bytes(dict(N=2048, box_min=(0, 0, 0), L=1.0, dn=2, nbins=512, ell_max=4), 10, 10, slabs=True)
     assert "fft_y" not in s and s["assign_x"] > s["fft_z_bin"]

@@ -86,14 +86,14 @@ def test_status_strings_and_result_size():
 
 
 def test_slab_plans():
-    """Slab height of the x and y transforms: all planes up to N = 1024 (the whole set fits
-    in 128 GiB), out of core at 2048 (22 grids would take 756 GB); with slabs the workspace
-    holds two of them and shrinks by exactly the planes not held."""
+    """Slab height of the x and y transforms: all planes up to N = 1024 (the 15 stored
+    grids fit in 128 GiB), out of core at 2048 (they would take 515 GB); with slabs the
+    workspace holds two of them and shrinks by exactly the planes not held."""
     assert native.x_planes(cfg(), 10, 100) == 64
     assert native.x_planes(cfg(N=1024, nbins=256, dn=2), 10, 100) == 1024
     c2048 = cfg(N=2048, nbins=512, dn=2, L=3500.0)
-    # one plane of the 22 grids: 22 * 2048 rows * 1024 kx * 8 bytes; 8 planes fit in 4 GiB
-    assert native.x_planes(c2048, 525000, 5250000) == 8   # two slots of 8 planes within 8 GiB
+    # one plane of the 15 stored grids: 15 * 2048 rows * 1024 kx * 8 bytes; 16 planes fit in 4 GiB
+    assert native.x_planes(c2048, 525000, 5250000) == 16   # two slots of 16 planes within 8 GiB
     assert native.x_planes(dict(c2048, ell_max=0), 10, 100) == 2048   # 1 grid: 34 GB
     total = native.workspace_size(c2048, 525000, 5250000)
     assert total < 280 * 2 ** 30, total / 2 ** 30
@@ -102,18 +102,18 @@ def test_slab_plans():
         small = native.workspace_size(cfg(x_planes=xs), 10, 100)
         assert native.x_planes(cfg(x_planes=xs), 10, 100) == xs
         # two slots of xs planes; Kx = nbins * dn = 32 columns at N = 64
-        assert full - small == 22 * (64 - 2 * xs) * 64 * 32 * 8
+        assert full - small == 15 * (64 - 2 * xs) * 64 * 32 * 8
 
 
 def test_schedule_table():
     """The column-transform schedule table: defaults, round trip and rejected values."""
-    assert native.get_schedule(512, 4) == (16, 8)   # defaults: 16 for y, 8 for z
-    native.set_schedule(256, 2, 8, 16)
+    assert native.get_schedule(512, 4) == (8, 8)   # defaults: 8 for both passes
+    native.set_schedule(256, 2, 16, 16)
     try:
-        assert native.get_schedule(256, 2) == (8, 16)
-        assert native.get_schedule(256, 4) == (16, 8)   # keyed by (N, ell_max)
+        assert native.get_schedule(256, 2) == (16, 16)
+        assert native.get_schedule(256, 4) == (8, 8)   # keyed by (N, ell_max)
     finally:
-        native.set_schedule(256, 2, 16, 8)
+        native.set_schedule(256, 2, 8, 8)
     assert native.get_schedule(2048, 4) == (8, 8)   # the only schedule built at 2048
     native.set_schedule(2048, 4, 8, 8)
     for bad in [(500, 4, 16, 16), (512, 3, 16, 16), (512, 4, 12, 16), (512, 4, 16, 4), (2048, 4, 16, 8)]:

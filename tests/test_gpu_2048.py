@@ -17,6 +17,7 @@ import time
 import numpy as np
 import pytest
 
+from conftest import x_row
 from oracle import direct
 from oracle import estimator as est
 from paper_1505_05341_amd import catalogs
@@ -89,11 +90,11 @@ def test_survey_shell_2048(pk):
 
 
 def _slab_catalogue(n, box_min, L, H, seed):
-    """Uniform points in the first 10 planes and the top 2 planes of the box (so that the
+    """Uniform points in the first 20 planes and the top 2 planes of the box (so that the
     first slab's rows have particles, including those reached across the periodic wrap)."""
     rng = np.random.default_rng(seed)
     pos = np.asarray(box_min, np.float64)[None, :] + rng.random((n, 3)) * L
-    zlo = box_min[2] + rng.random(n) * 10 * H
+    zlo = box_min[2] + rng.random(n) * 20 * H
     zhi = box_min[2] + L - rng.random(n) * 2 * H
     pos[:, 2] = np.where(rng.random(n) < 0.8, zlo, zhi)
     nbar = np.full(n, 1e-4, np.float32)
@@ -124,11 +125,9 @@ def test_first_slab_rows_2048(pk, assign):
         iy = int(rng.integers(0, N))
         l1 = est.x_transformed_row(pos, np.abs(wp), c, (0, 0, 0), iy, iz)[0].real
         assert l1 > 0
-        for m in (0, 6, 21):
-            X = pk.xgrid_view(ws, layout, m, N)
-            kx = layout[m][1]
-            row = X[iz, iy].cpu().numpy()
-            row = row[:, 0] + 1j * row[:, 1]
+        for m in (0, 6, 21):   # 6 and 21: combinations of stored rows
+            kx = layout[0][1]
+            row = x_row(pk, ws, layout, m, N, iz, iy)
             ref = est.x_transformed_row(pos, wp, c, native.monomial(m), iy, iz)[:kx]
             err = np.max(np.abs(row - ref)) / l1
             print("row", (iy, iz), "grid", m, "err %.2e" % err, flush=True)

@@ -17,6 +17,7 @@ import time
 import numpy as np
 import pytest
 
+from conftest import x_row
 from oracle import direct
 from oracle import estimator as est
 from paper_1505_05341_amd import catalogs
@@ -71,11 +72,9 @@ def test_sampled_x_rows_full_size(workload):
         sub_pos, sub_w = pos[near], wp[near]
         # sum over the row of |w'| W_x W_y W_z: bounds the sum of |terms| of every grid
         l1 = est.x_transformed_row(sub_pos, np.abs(sub_w), c, (0, 0, 0), iy, iz)[0].real
-        for m in (0, 4, 17, 21):   # 21 (rhat_z^4) is written from the gathered monomials
-            X = pk.xgrid_view(ws, layout, m, N)
-            kx = layout[m][1]
-            got = X[iz, iy].cpu().numpy()
-            got = got[:, 0] + 1j * got[:, 1]
+        for m in (0, 4, 17, 21):   # 21 (rhat_z^4) is the identity's combination of stored rows
+            kx = layout[0][1]
+            got = x_row(pk, ws, layout, m, N, iz, iy)
             ref = est.x_transformed_row(sub_pos, sub_w, c, native.monomial(m), iy, iz)[:kx]
             err = np.max(np.abs(got - ref)) / l1
             print("row", (iy, iz), "grid", m, "particles", int(near.sum()), "err %.2e" % err, flush=True)
@@ -176,11 +175,9 @@ def test_sampled_x_rows_desi_1024(assign):
         sub_pos = np.concatenate([gp, rp])
         sub_w = est.signed_weights(gw, rw, alpha)
         l1 = est.x_transformed_row(sub_pos, np.abs(sub_w), c, (0, 0, 0), iy, iz)[0].real
-        for m in (0, 6, 21):
-            kx = layout[m][1]
-            X = pk.xgrid_view(ws, layout, m, N)
-            got = X[iz, iy].cpu().numpy()
-            got = got[:, 0] + 1j * got[:, 1]
+        for m in (0, 6, 21):   # 6 and 21: combinations of stored rows
+            kx = layout[0][1]
+            got = x_row(pk, ws, layout, m, N, iz, iy)
             ref = est.x_transformed_row(sub_pos, sub_w, c, native.monomial(m), iy, iz)[:kx]
             err = np.max(np.abs(got - ref)) / l1
             print("row", (iy, iz), "grid", m, "particles", len(sub_pos), "err %.2e" % err, flush=True)

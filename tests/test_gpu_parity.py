@@ -7,6 +7,7 @@ power is the scale FP32 rounding acts on); k_eff to 1e-6 relative.
 import numpy as np
 import pytest
 
+from conftest import x_row
 from oracle import estimator as est
 from paper_1505_05341_amd import catalogs
 
@@ -112,8 +113,8 @@ def test_small_clustered_tsc_dn2(pk):
 
 def test_xgrid_rows_match_oracle(pk):
     """Stage check: sampled rows of all 22 x-transformed LOS-weighted grids (the 15 gathered
-    ones and the 7 with a power of rhat_z of 2 or more, written from the identity
-    sum_i rhat_i^2 = 1)."""
+    and stored ones, and the 7 with a power of rhat_z of 2 or more as the combinations of
+    stored rows that the identity sum_i rhat_i^2 = 1 gives, which the y pass forms)."""
     import torch
     gal, ran, cfg = catalogs.small_clustered(N=64, nbar=3e-4, ran_factor=10.0, assign=3)
     g = pk.DeviceCatalog.from_host(gal)
@@ -125,19 +126,19 @@ def test_xgrid_rows_match_oracle(pk):
     wp = est.signed_weights(gal.w, ran.w, alpha)
     rng = np.random.default_rng(0)
     from paper_1505_05341_amd import native
+    assert sorted(layout) == [m for m in range(22) if native.monomial(m)[2] <= 1]  # the 15 stored
     for m in range(22):
-        X = pk.xgrid_view(ws, layout, m, c.N).cpu().numpy()
         mono = native.monomial(m)
         for _ in range(3):
-            iy, iz = rng.integers(0, c.N, 2)
+            iy, iz = (int(v) for v in rng.integers(0, c.N, 2))
             ref = est.x_transformed_row(pos, wp, c, mono, iy, iz)
             # FP32 rounding scales with the sum of |terms| of the row (the row itself is a
             # density contrast, and grids such as rhat_x rhat_y change sign), which the
             # x-transformed |w'| row bounds at kx = 0 (|rhat^m| <= 1); a lost particle
             # would be ~1/1500 of it
             l1 = est.x_transformed_row(pos, np.abs(wp), c, (0, 0, 0), iy, iz)[0].real
-            kx = layout[m][1]
-            gotrow = X[iz, iy, :, 0] + 1j * X[iz, iy, :, 1]
+            kx = layout[0][1]
+            gotrow = x_row(pk, ws, layout, m, c.N, iz, iy)
             err = np.max(np.abs(gotrow - ref[:kx])) / l1
             assert err < 1e-5, (m, iy, iz, err)
 
@@ -176,7 +177,7 @@ def test_ell6_xgrid_rows(pk):
     g = pk.DeviceCatalog.from_host(gal)
     r = pk.DeviceCatalog.from_host(ran)
     ws, layout = pk.stage_xgrids(g, r, cfg)
-    assert len(layout) == 50
+    assert len(layout) == 28
     c = est.Config(**cfg)
     alpha, I, S = est.catalogue_scalars(gal.w, ran.w, gal.nbar, ran.nbar)
     pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
@@ -185,10 +186,9 @@ def test_ell6_xgrid_rows(pk):
     iy, iz = (int(v) for v in rng.integers(0, c.N, 2))
     l1 = est.x_transformed_row(pos, np.abs(wp), c, (0, 0, 0), iy, iz)[0].real
     for m in range(50):
-        X = pk.xgrid_view(ws, layout, m, c.N).cpu().numpy()
-        kx = layout[m][1]
+        kx = layout[0][1]
         ref = est.x_transformed_row(pos, wp, c, native.monomial(m), iy, iz)[:kx]
-        err = np.max(np.abs(X[iz, iy, :, 0] + 1j * X[iz, iy, :, 1] - ref)) / l1
+        err = np.max(np.abs(x_row(pk, ws, layout, m, c.N, iz, iy) - ref)) / l1
         assert err < 1e-5, (m, err)
 
 
@@ -369,7 +369,7 @@ def test_every_schedule_matches_oracle(pk, N):
         assert native.get_schedule(N, cfg["ell_max"]) == best
         compare(pk.pk_multipoles(g, r, cfg), ref, cfg)
     finally:
-        native.set_schedule(N, cfg["ell_max"], 16, 8)   # back to the defaults
+        native.set_schedule(N, cfg["ell_max"], 8, 8)   # back to the defaults
 
 
 @pytest.mark.parametrize("N,assign,xs", [(32, 2, 1), (32, 3, 4), (64, 3, 8), (64, 2, 32)])
@@ -393,15 +393,14 @@ def test_slabs_match_oracle(pk, N, assign, xs):
     pos = np.concatenate([gal.pos, ran.pos]).astype(np.float64)
     wp = est.signed_weights(gal.w, ran.w, alpha)
     rng = np.random.default_rng(N + xs)
-    for m in (0, 6, 21):
-        X = pk.xgrid_view(ws, layout, m, N).cpu().numpy()
-        assert X.shape[0] == xs
+    assert pk.xgrid_view(ws, layout, 0, N).shape[0] == xs
+    for m in (0, 6, 21):   # 6 (rhat_z^2) and 21 (rhat_z^4) from the stored rows
         mono = native.monomial(m)
         for iz in sorted({0, xs - 1}):
             iy = int(rng.integers(0, N))
             ref_row = est.x_transformed_row(pos, wp, c, mono, iy, iz)
-            kx = layout[m][1]
-            gotrow = X[iz, iy, :, 0] + 1j * X[iz, iy, :, 1]
+            kx = layout[0][1]
+            gotrow = x_row(pk, ws, layout, m, N, iz, iy)
             scale = np.sqrt(np.mean(np.abs(ref_row[:kx]) ** 2)) + 1e-30
             assert np.max(np.abs(gotrow - ref_row[:kx])) / scale < 1e-5, (m, iy, iz)
     del ws
@@ -415,7 +414,7 @@ def test_slabs_match_oracle(pk, N, assign, xs):
             assert best[0] in (8, 16) and best[1] in (8, 16)
             compare(pk.pk_multipoles(g, r, scfg), ref, cfg)
         finally:
-            native.set_schedule(N, cfg["ell_max"], 16, 8)   # back to the defaults
+            native.set_schedule(N, cfg["ell_max"], 8, 8)   # back to the defaults
 
 
 # ------------------------------------------------------------------------- degenerate inputs
