@@ -200,13 +200,13 @@ pk_status pk_stage_xgrids(const pk_config* cfg, const pk_catalog* gal, const pk_
 /* Where pk_stage_xgrids leaves grid `m` (a monomial with a power of rhat_z below 2: only
  * those are stored, 1, 6, 15 or 28 of the 1, 7, 22 or 50; any other monomial is an integer
  * combination of them through rhat_x^2 + rhat_y^2 + rhat_z^2 = 1, which the y transform
- * applies, and returns PK_EINVAL here): complex64 values X[z][y][kx] for z < x_planes
- * (pk_x_planes), y < N, kx < kx_count: the x-transformed (unnormalised,
- * e^{-2 pi i kx x / N}) row of F rhat^m at (y, z), starting at byte `offset` of the
- * workspace. At N = 2048 the values are stored tile-major, X[z][kx / 4][y][kx % 4]
- * (4-column tiles, so that the y transform reads each tile as one contiguous run).
- * Monomial m has exponents (a, b, c) of rhat_x, rhat_y, rhat_z as returned by
- * pk_monomial. */
+ * applies, and returns PK_EINVAL here): for z < x_planes (pk_x_planes), y < N,
+ * kx < kx_count, the x-transformed (unnormalised, e^{-2 pi i kx x / N}) row of F rhat^m at
+ * (y, z), complex64 values starting at byte `offset` of the workspace and stored
+ * tile-major, X[z][kx / W][y][kx % W], with W the tile width pk_hgrid_layout reports
+ * (16 up to N = 512, 8 at 1024, 4 at 2048), so that the y transform reads each tile of a
+ * plane as one contiguous run. Monomial m has exponents (a, b, c) of rhat_x, rhat_y,
+ * rhat_z as returned by pk_monomial. */
 pk_status pk_xgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t m,
                           size_t* offset, int32_t* kx_count);
 

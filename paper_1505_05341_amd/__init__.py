@@ -6,4 +6,4 @@ this package is its Python binding plus the seeded synthetic catalogue generator
 """
 from .native import PkError, get_schedule, load, set_schedule  # noqa: F401
 from .api import (DeviceCatalog, Workspace, autotune, pk_multipoles, pk_multipoles_batch,  # noqa: F401
-                  hgrid_view, stage_contract, stage_fft, stage_xgrids, xgrid_view)
+                  hgrid_view, stage_contract, stage_fft, stage_xgrids, xgrid_row, xgrid_view)

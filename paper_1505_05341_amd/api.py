@@ -138,9 +138,10 @@ def pk_multipoles_batch(gals, rans, cfgs, lanes: int = 2, workspace: Workspace |
 
 def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: Workspace | None = None):
     """Runs up to the fused assignment + x transform of the first slab of planes and
-    returns (workspace tensor, layout), layout[m] = (byte offset, kx_count, planes) of grid
-    m (complex64 X[z][y][kx] for z < planes) for every stored grid: the monomials with a
-    power of rhat_z below 2 (the others follow from them, rhat_z^2 = 1 - rhat_x^2 - rhat_y^2)."""
+    returns (workspace tensor, layout), layout[m] = (byte offset, kx_count, planes, tile
+    width W) of grid m (complex64 X[z][kx / W][y][kx % W] for z < planes; see xgrid_view)
+    for every stored grid: the monomials with a power of rhat_z below 2 (the others follow
+    from them, rhat_z^2 = 1 - rhat_x^2 - rhat_y^2)."""
     import torch
     lib = native.load()
     c = native.make_config(cfg)
@@ -151,13 +152,16 @@ def stage_xgrids(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, workspace: W
     torch.cuda.synchronize()
     layout = {}
     planes = native.x_planes(cfg, gal.n, ran.n)
+    hoff, hm, width = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int32()
+    native.check(lib.pk_hgrid_layout(ctypes.byref(c), gal.n, ran.n, 0, 0, ctypes.byref(hoff), ctypes.byref(hm),
+                                     ctypes.byref(width)))
     for m in range(native.num_grids(c.ell_max)):
         if native.monomial(m)[2] > 1:
             continue
         off = ctypes.c_size_t()
         kx = ctypes.c_int32()
         native.check(lib.pk_xgrid_layout(ctypes.byref(c), gal.n, ran.n, m, ctypes.byref(off), ctypes.byref(kx)))
-        layout[m] = (int(off.value), int(kx.value), planes)
+        layout[m] = (int(off.value), int(kx.value), planes, int(width.value))
     return ws, layout
 
 
@@ -204,15 +208,22 @@ def stage_contract(ws, cfg: dict, n_gal: int, n_ran: int):
 
 def xgrid_view(ws, layout, m, N):
     """complex64 values X[z][y][kx] (z < the slab height) of grid m inside the workspace
-    returned by stage_xgrids, as (planes, N, kx, 2) float32: a view, or at N = 2048, where
-    the library stores X tile-major ([z][kx / 4][y][kx % 4]), a reordered copy."""
+    returned by stage_xgrids, as (planes, N, kx, 2) float32: a strided view of the
+    library's tile-major storage ([z][kx / W][y][kx % W], W = the tile width)."""
     import torch
-    off, kx, planes = layout[m]
+    off, kx, planes, w = layout[m]
     nbytes = planes * N * kx * 8
     raw = ws[off:off + nbytes].view(torch.float32)
-    if N >= 2048:
-        return raw.view(planes, kx // 4, N, 4, 2).permute(0, 2, 1, 3, 4).reshape(planes, N, kx, 2)
-    return raw.view(planes, N, kx, 2)
+    return raw.view(planes, kx // w, N, w, 2).permute(0, 2, 1, 3, 4).reshape(planes, N, kx, 2)
+
+
+def xgrid_row(ws, layout, m, N, z, y):
+    """Row (z, y) of grid m of the stage_xgrids workspace as (kx, 2) float32 (a copy of
+    that row only: xgrid_view reorders the whole tile-major grid)."""
+    import torch
+    off, kx, planes, w = layout[m]
+    raw = ws[off:off + planes * N * kx * 8].view(torch.float32)
+    return raw.view(planes, kx // w, N, w, 2)[z, :, y].reshape(kx, 2)
 
 
 def autotune(gal: DeviceCatalog, ran: DeviceCatalog, cfg: dict, reps: int = 3, workspace: Workspace | None = None):

@@ -36,6 +36,13 @@ enum FlagBits {
   kFlagBadNorm = 16
 };
 
+// kx columns per tile of X (tile-major, written by the x pass) and of H (y and z passes):
+// 16 (128-byte rows) up to N = 512; 8 at N = 1024, where a 16-column tile would need
+// 1024-thread y blocks and their 128-register cap; 4 at 2048, where the 8-value schedule
+// needs 256 threads per column.
+template <int N>
+__host__ __device__ constexpr int tile_cols() { return N >= 2048 ? 4 : (N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16)); }
+
 // Exponents of monomial m in the fixed order used everywhere: degree 0, 2, 4, then 6,
 // each with the power of x descending, then the power of y descending.
 struct Monomial { int a, b, c; };

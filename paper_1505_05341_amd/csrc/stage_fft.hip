@@ -53,12 +53,6 @@ struct ColSlot {
   __device__ __forceinline__ int operator()(int idx) const { return idx * TK + c; }
 };
 
-// kx columns per tile: 16 (128-byte rows) up to N = 512; 8 at N = 1024, where a
-// 16-column tile would need 1024-thread blocks and their 128-register cap; 4 at 2048,
-// where the 8-value schedule needs 256 threads per column.
-template <int N>
-constexpr int tile_cols() { return N >= 2048 ? 4 : (N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16)); }
-
 // kx columns per y-pass block: half a tile of H at N = 512 and 1024, so that two blocks
 // (8 and 16 values per thread respectively need 96 and ~230 registers) share a CU and
 // one block's barriers overlap the other's work; two neighbouring blocks (on one XCD)
@@ -99,18 +93,14 @@ __device__ __forceinline__ void load_member(const float2* __restrict__ X, const 
   using F = Fft<N, EC>;
   const int tid = col_hide<EC>(tid0);
   const int c = tid % TK, t = tid / TK;
-  if constexpr (N >= 2048) {  // tile-major X: [plane][kx / TK][y][kx % TK]
-    static_assert(TK == 4, "tile-major X is written with 4-column tiles");
-    const float2* __restrict__ src =
-        X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + (size_t)kt * TK * N + c;
+  // tile-major X: [plane][kx / TW][y][kx % TW], the block's TK columns inside one tile
+  constexpr int TW = tile_cols<N>();
+  static_assert(TW % TK == 0, "a y block reads a part of one X tile");
+  const int kx = kt * TK + c;
+  const float2* __restrict__ src =
+      X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + (size_t)(kx / TW) * TW * N + (kx % TW);
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * TK];
-  } else {
-    const float2* __restrict__ src =
-        X + (size_t)m * a.x_grid_stride + (size_t)(a.pbase + zs) * N * a.Kx + kt * TK + c;
-#pragma unroll
-    for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * a.Kx];
-  }
+  for (int e = 0; e < F::E; ++e) d[e] = src[(size_t)F::in_index(t, e) * TW];
 }
 
 // One set of z-power groups (YSetTable) for TK kx columns at one z: every member (a

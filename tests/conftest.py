@@ -35,6 +35,6 @@ def x_row(pk, ws, layout, m, N, iz, iy):
     index = {tuple(native.monomial(i)): i for i in layout}
     row = 0
     for mono, wgt in gathered_weights(*native.monomial(m)).items():
-        r = pk.xgrid_view(ws, layout, index[mono], N)[iz, iy].cpu().numpy().astype(np.float64)
+        r = pk.xgrid_row(ws, layout, index[mono], N, iz, iy).cpu().numpy().astype(np.float64)
         row = row + wgt * (r[:, 0] + 1j * r[:, 1])
     return row
