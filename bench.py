@@ -40,10 +40,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = ["paper_1505_05341_amd/csrc/" + f for f in
                  ("stage_assign.hip", "particle.hpp", "fft_dev.hpp", "plan.hpp", "dft_consts.h", "basis.hpp")]
 TRAFFIC = {
-    ("clustered_512", "assign_x"): {"sha256": "ff4d0a8d05eed4222d0a6b74ab3da5a81a492a6a1b73c2c9818c7a292efb243c",
-                 "fetch_kib": 870905.0, "write_kib": 7864320.0, "fetch_scale": 2.0, "write_scale": 1.0},
-    ("desi_1024", "assign_x"): {"sha256": "ff4d0a8d05eed4222d0a6b74ab3da5a81a492a6a1b73c2c9818c7a292efb243c",
-                 "fetch_kib": 6227070.0, "write_kib": 62914560.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    ("clustered_512", "assign_x"): {"sha256": "feb6d88ccdc596708e15857fc30706103c1eefbb7aaa6a6a024bfbeea73283fb",
+                 "fetch_kib": 879365.0, "write_kib": 7864320.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    ("desi_1024", "assign_x"): {"sha256": "feb6d88ccdc596708e15857fc30706103c1eefbb7aaa6a6a024bfbeea73283fb",
+                 "fetch_kib": 7751049.0, "write_kib": 66893824.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
