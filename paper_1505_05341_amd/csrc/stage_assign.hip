@@ -25,6 +25,7 @@
 
 #include "basis.hpp"
 #include "fft_dev.hpp"
+#include "monomial_sums.hpp"
 #include "particle.hpp"
 #include "plan.hpp"
 
@@ -103,53 +104,10 @@ __device__ __forceinline__ void scan_counts(uint32_t* cnt, uint32_t* st) {
 
 // Adds a chunk particle (pa = (f, w W_y W_z, rx, ry), rz) with stencil offset o along x to
 // the NG kept-monomial sums of a target cell: CIC weights (1 - f, f) for o = (0, 1); TSC
-// 3/4 - d^2 for o = 0 and (1/2 + o d)^2 / 2 for o = +-1. Each product w rhat^m is one
-// multiply-add from two factors already at hand: w rhat_x^2 and w rhat_y^2 times a monomial
-// two degrees lower, which takes 24 vector operations for the 15 sums of ell_max = 4 where
-// forming every monomial and then w times it takes 29.
+// 3/4 - d^2 for o = 0 and (1/2 + o d)^2 / 2 for o = +-1.
 template <int NG, int ASSIGN>
 __device__ __forceinline__ void add_particle(float (&acc)[NG], const float4 p, const float rz, const int o) {
-  const float w = p.y * stencil_weight<ASSIGN>(p.x, o);
-  const float rx = p.z, ry = p.w;
-  acc[0] += w;
-  if constexpr (NG > 1) {
-    const float wx = w * rx, wy = w * ry;
-    const float wxx = wx * rx, wyy = wy * ry;
-    acc[1] += wxx;      // 200
-    acc[2] += wx * ry;  // 110
-    acc[3] += wx * rz;  // 101
-    acc[4] += wyy;      // 020
-    acc[5] += wy * rz;  // 011
-    if constexpr (NG > 6) {
-      const float xx = rx * rx, xy = rx * ry, xz = rx * rz, yy = ry * ry, yz = ry * rz;
-      acc[6] += wxx * xx;   // 400
-      acc[7] += wxx * xy;   // 310
-      acc[8] += wxx * xz;   // 301
-      acc[9] += wxx * yy;   // 220
-      acc[10] += wxx * yz;  // 211
-      acc[11] += wyy * xy;  // 130
-      acc[12] += wyy * xz;  // 121
-      acc[13] += wyy * yy;  // 040
-      acc[14] += wyy * yz;  // 031
-      if constexpr (NG > 15) {
-        const float m400 = xx * xx, m310 = xx * xy, m301 = xx * xz, m220 = xx * yy, m211 = xx * yz;
-        const float m130 = yy * xy, m121 = yy * xz, m040 = yy * yy, m031 = yy * yz;
-        acc[15] += wxx * m400;  // 600
-        acc[16] += wxx * m310;  // 510
-        acc[17] += wxx * m301;  // 501
-        acc[18] += wxx * m220;  // 420
-        acc[19] += wxx * m211;  // 411
-        acc[20] += wxx * m130;  // 330
-        acc[21] += wxx * m121;  // 321
-        acc[22] += wxx * m040;  // 240
-        acc[23] += wxx * m031;  // 231
-        acc[24] += wyy * m130;  // 150
-        acc[25] += wyy * m121;  // 141
-        acc[26] += wyy * m040;  // 060
-        acc[27] += wyy * m031;  // 051
-      }
-    }
-  }
+  add_monomial_sums<NG>(acc, p.y * stencil_weight<ASSIGN>(p.x, o), p.z, p.w, rz);
 }
 
 // Gathers the NG kept monomial rows of the block's target row into LDS rows[g][x]
