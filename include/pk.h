@@ -230,6 +230,20 @@ pk_status pk_stage_fft(const pk_config* cfg, const pk_catalog* gal, const pk_cat
 pk_status pk_hgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, int32_t group, int32_t kx_tile,
                           size_t* offset, int32_t* ky_max, int32_t* tile_cols);
 
+/* Inspection entry point for tests (host only, no GPU): the weights with which the y
+ * transform forms the z-power groups from the stored grids (pk_xgrid_layout), with sets of
+ * up to `max_groups` groups per launch (6: the 8-value y schedule up to N = 512; 3: the
+ * 16-value schedule, and the 8-value one from N = 1024 on). Term i adds
+ * coef[i] tx^a[i] ty^b[i] Y_grid[i] to H_group[i] (Y: the grid transformed along x and y;
+ * grid[i] a monomial index as for pk_monomial, group[i] as for pk_zgroup), in launch
+ * set[i]; over all terms, sum_c tz^c H_(n,c) = sum_{a+b+c=n} (n!/(a! b! c!)) tx^a ty^b tz^c
+ * Y_abc with every monomial of power of rhat_z of 2 or more written through
+ * rhat_x^2 + rhat_y^2 + rhat_z^2 = 1 (Sec. 3, Eqs. 10 and 12). Writes the first `cap` terms
+ * into the caller's arrays and returns the number of terms; -1 (PK_EINVAL detail) for an
+ * unsupported ell_max or max_groups, or null arrays with cap > 0. */
+int32_t pk_ygroup_terms(int32_t ell_max, int32_t max_groups, int32_t cap, int32_t* set, int32_t* group,
+                        int32_t* grid, float* coef, int32_t* a, int32_t* b);
+
 /* Degree n and power c of tz of z-power group `group`: the groups run over n = 0, 2, ..
  * ell_max and, for each n, c = 0 .. n. PK_EINVAL past the last group. */
 pk_status pk_zgroup(int32_t ell_max, int32_t group, int32_t* degree, int32_t* z_power);

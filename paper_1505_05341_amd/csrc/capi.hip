@@ -69,6 +69,29 @@ static int log2_of(int N) {
   return l;
 }
 
+// Groups (n, c) and their members (grid index, a, b, multinomial weight n!/(a! b! c!)).
+static void build_groups(int ell, GroupTable* gt) {
+  static const int fact[7] = {1, 1, 2, 6, 24, 120, 720};
+  gt->ngroups = 0;
+  for (int n = 0; n <= ell; n += 2) {
+    for (int c = 0; c <= n; ++c) {
+      const int g = gt->ngroups++;
+      gt->n[g] = n;
+      gt->c[g] = c;
+      gt->count[g] = 0;
+      for (int m = 0; m < num_grids_for(ell); ++m) {
+        const Monomial mo = monomial(m);
+        if (mo.a + mo.b + mo.c != n || mo.c != c) continue;
+        const int s = gt->count[g]++;
+        gt->grid[g][s] = m;
+        gt->a[g][s] = mo.a;
+        gt->b[g][s] = mo.b;
+        gt->coef[g][s] = (float)(fact[n] / (fact[mo.a] * fact[mo.b] * fact[mo.c]));
+      }
+    }
+  }
+}
+
 // Sets of the y pass (see YSetTable) for groups of at most gmax: the groups of each parity
 // of c in order, gmax at a time; a set's members are the gathered grids, in gathered order,
 // that carry a term of one of its groups. A member (a, b, c) of group (n, c) with weight
@@ -193,28 +216,8 @@ pk_status make_plan(const pk_config* cfg, int64_t n_gal, int64_t n_ran, Plan* pl
   p.col_e[0] = p.N >= 2048 ? 8 : (sc.y ? sc.y : 8);  // only the 8-value schedule is built at 2048
   p.col_e[1] = p.N >= 2048 ? 8 : (sc.z ? sc.z : 8);
 
-  // groups (n, c) and their members (grid index, a, b, multinomial weight)
   GroupTable& gt = p.groups;
-  gt.ngroups = 0;
-  for (int n = 0; n <= p.ell_max; n += 2) {
-    for (int c = 0; c <= n; ++c) {
-      const int g = gt.ngroups++;
-      gt.n[g] = n;
-      gt.c[g] = c;
-      gt.count[g] = 0;
-      for (int m = 0; m < p.G; ++m) {
-        const Monomial mo = monomial(m);
-        if (mo.a + mo.b + mo.c != n || mo.c != c) continue;
-        static const int fact[7] = {1, 1, 2, 6, 24, 120, 720};
-        const int s = gt.count[g]++;
-        gt.grid[g][s] = m;
-        gt.a[g][s] = mo.a;
-        gt.b[g][s] = mo.b;
-        gt.coef[g][s] = (float)(fact[n] / (fact[mo.a] * fact[mo.b] * fact[mo.c]));
-      }
-    }
-  }
-
+  build_groups(p.ell_max, &gt);
   build_ysets(gt, p.ell_max, kYSetGroups, &p.ysets[0]);
   build_ysets(gt, p.ell_max, 3, &p.ysets[1]);
 
@@ -836,6 +839,32 @@ pk_status pk_hgrid_layout(const pk_config* cfg, int64_t n_gal, int64_t n_ran, in
   *ky_max = p.tiles.M[kx_tile];
   *tile_cols = p.TK;
   return PK_OK;
+}
+
+int32_t pk_ygroup_terms(int32_t ell_max, int32_t max_groups, int32_t cap, int32_t* set, int32_t* group,
+                        int32_t* grid, float* coef, int32_t* a, int32_t* b) {
+  if (!ell_ok(ell_max) || (max_groups != 3 && max_groups != kYSetGroups) || cap < 0 ||
+      (cap > 0 && (!set || !group || !grid || !coef || !a || !b))) {
+    fail(PK_EINVAL, "bad ell_max, max_groups or output arrays");
+    return -1;
+  }
+  GroupTable gt;
+  YSetTable yt;
+  build_groups(ell_max, &gt);
+  build_ysets(gt, ell_max, max_groups, &yt);
+  int32_t k = 0;
+  for (int s = 0; s < yt.nsets; ++s)
+    for (int i = yt.mem0[s]; i < yt.mem0[s + 1]; ++i)
+      for (int q = yt.term0[i]; q < yt.term0[i + 1]; ++q, ++k)
+        if (k < cap) {
+          set[k] = s;
+          group[k] = yt.group[s][yt.tslot[q]];
+          grid[k] = kept_monomial(yt.mgrid[i]);
+          coef[k] = yt.tcoef[q];
+          a[k] = yt.ta[q];
+          b[k] = yt.tb[q];
+        }
+  return k;
 }
 
 pk_status pk_zgroup(int32_t ell_max, int32_t group, int32_t* degree, int32_t* z_power) {

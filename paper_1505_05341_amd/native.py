@@ -46,7 +46,7 @@ EXPORTS = ["pk_workspace_size", "pk_multipoles", "pk_multipoles_async", "pk_resu
            "pk_stage_xgrids", "pk_xgrid_layout", "pk_num_grids", "pk_monomial", "pk_status_string",
            "pk_last_error", "pk_last_error_detail", "pk_set_stage_timing", "pk_stage_times", "pk_stage_name",
            "pk_workspace_size_batch", "pk_multipoles_batch", "pk_set_schedule", "pk_get_schedule", "pk_autotune",
-           "pk_x_planes", "pk_stage_fft", "pk_stage_contract", "pk_hgrid_layout", "pk_zgroup"]
+           "pk_x_planes", "pk_stage_fft", "pk_stage_contract", "pk_hgrid_layout", "pk_zgroup", "pk_ygroup_terms"]
 
 _lib = None
 
@@ -74,6 +74,9 @@ def load():
     lib.pk_hgrid_layout.argtypes = [P(PkConfig), c_int64, c_int64, c_int32, c_int32, P(c_size_t), P(c_int32),
                                     P(c_int32)]
     lib.pk_zgroup.argtypes = [c_int32, c_int32, P(c_int32), P(c_int32)]
+    lib.pk_ygroup_terms.argtypes = [c_int32, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32),
+                                    P(ctypes.c_float), P(c_int32), P(c_int32)]
+    lib.pk_ygroup_terms.restype = c_int32
     lib.pk_num_grids.argtypes = [c_int32]
     lib.pk_num_grids.restype = c_int32
     lib.pk_monomial.argtypes = [c_int32, P(c_int32), P(c_int32), P(c_int32)]
@@ -97,10 +100,24 @@ def load():
     lib.pk_stage_name.restype = c_char_p
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype if name in (
-            "pk_result_doubles", "pk_num_grids", "pk_status_string", "pk_last_error", "pk_last_error_detail", "pk_stage_times",
+            "pk_result_doubles", "pk_num_grids", "pk_status_string", "pk_last_error", "pk_last_error_detail",
+            "pk_ygroup_terms", "pk_stage_times",
             "pk_stage_name") else c_int32
     _lib = lib
     return lib
+
+
+def ygroup_terms(ell_max, max_groups):
+    """The y pass's weight table (pk_ygroup_terms) as a list of (set, group, grid, coef, a, b)."""
+    lib = load()
+    n = lib.pk_ygroup_terms(int(ell_max), int(max_groups), 0, None, None, None, None, None, None)
+    if n < 0:
+        raise PkError(-1, last_error())
+    arr = {k: (c_int32 * n)() for k in ("set", "group", "grid", "a", "b")}
+    coef = (ctypes.c_float * n)()
+    lib.pk_ygroup_terms(int(ell_max), int(max_groups), n, arr["set"], arr["group"], arr["grid"], coef, arr["a"],
+                        arr["b"])
+    return [(arr["set"][i], arr["group"][i], arr["grid"][i], coef[i], arr["a"][i], arr["b"][i]) for i in range(n)]
 
 
 def last_error():

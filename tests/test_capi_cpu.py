@@ -4,6 +4,7 @@ monomial table) behaves; nothing here launches a kernel."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1505_05341_amd import native
@@ -120,3 +121,50 @@ def test_schedule_table():
         with pytest.raises(native.PkError) as ei:
             native.set_schedule(*bad)
         assert ei.value.status == -1
+
+
+def test_y_pass_weights_reproduce_the_contraction():
+    """The y pass's weight table (pk_ygroup_terms, built on the host from basis.hpp and the
+    multinomial weights): for random unit lines of sight rhat and random t, the terms of the
+    z-power groups of degree n, summed with tz^c, give (t . rhat)^n, the kernel of Eqs. (10)
+    and (12); every group lies in one launch set with at most max_groups groups, each
+    (group, stored grid, a, b) term occurs once, and every grid is a stored one (power of
+    rhat_z below 2)."""
+    import math
+    rng = np.random.default_rng(12)
+    for ell in (0, 2, 4, 6):
+        groups = []
+        g = 0
+        while True:
+            try:
+                groups.append(native.zgroup(ell, g))
+            except native.PkError:
+                break
+            g += 1
+        for max_groups in (3, 6):
+            terms = native.ygroup_terms(ell, max_groups)
+            sets = {}
+            for s, grp, grid, coef, a, b in terms:
+                sets.setdefault(s, set()).add(grp)
+                assert native.monomial(grid)[2] <= 1
+            assert all(len(v) <= max_groups for v in sets.values())
+            owner = [sorted(s for s, v in sets.items() if grp in v) for grp in range(len(groups))]
+            assert all(len(o) == 1 for o in owner), owner
+            keys = [(grp, grid, a, b) for _, grp, grid, _, a, b in terms]
+            assert len(keys) == len(set(keys))
+            # parity of the power of tz: a set's groups share it
+            for v in sets.values():
+                assert len({groups[grp][1] % 2 for grp in v}) == 1
+            for _ in range(20):
+                r = rng.normal(size=3)
+                r /= np.linalg.norm(r)
+                t = rng.normal(size=3)
+                got = np.zeros(ell // 2 + 1)
+                for _, grp, grid, coef, a, b in terms:
+                    n, c = groups[grp]
+                    ga, gb, gc = native.monomial(grid)
+                    got[n // 2] += coef * t[0] ** a * t[1] ** b * t[2] ** c * r[0] ** ga * r[1] ** gb * r[2] ** gc
+                want = np.array([np.dot(t, r) ** n for n in range(0, ell + 1, 2)])
+                np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-5 * max(1.0, np.max(np.abs(want))))
+    with pytest.raises(native.PkError):
+        native.ygroup_terms(4, 5)
